@@ -48,8 +48,8 @@ def hash64(x):
 
 
 def thresh_for_inv_sqrt(k):
-    """32-bit threshold thr = isqrt(floor(2^64 / k)), so P(bit) = thr / 2^32 ~ 1/sqrt(k)."""
-    return math.isqrt((1 << 64) // int(k))
+    """32-bit threshold thr = min(isqrt(floor(2^64 / k)), 2^32 - 1): P(bit) = thr / 2^32 ~ 1/sqrt(k)."""
+    return min(math.isqrt((1 << 64) // int(k)), 0xFFFFFFFF)
 
 
 class Dist:

@@ -1,0 +1,210 @@
+/* bmm: exact products of packed bit matrices on AMD Instinct MI355X (gfx950).
+ *
+ * Operations (Karppa & Kaski, "Engineering Boolean Matrix Multiplication for
+ * Multiple-Accelerator Shared-Memory Architectures", arXiv 1909.01554):
+ *   - the product of an m x k and a k x n bit matrix over the binary field
+ *     GF(2) = (0,1,+,*) and over the Boolean algebra (0,1,OR,AND) (section 1;
+ *     product definition in section 2.4), by the cubic bit-parallel method
+ *     (section 3.18);
+ *   - the GF(2) product by the self-inverse alternative-basis Strassen
+ *     recursion (Theorem 1, section 2.2; matrix form section 2.8; layers
+ *     sections 3.4-3.13): forward basis change of A and B, seven block products
+ *     per 2 x 2 level down to a cubic leaf, inverse basis change of C.
+ *
+ * LAYOUT.  Every matrix is packed row-major in 64-bit words: bit j of row i is
+ * bit (j % 64) of word i * ld + j / 64 (least significant bit first).  ld (the
+ * row pitch, in words) must be at least ceil(cols / 64).  Bits past the last
+ * column of a row (padding) must be zero in A and B; the library writes them
+ * as zero in C (with BMM_FLAG_ACCUMULATE it leaves them as they were).
+ *
+ * MEMORY AND OWNERSHIP.  A, B, C and workspaces are device pointers owned by
+ * the caller (for example PyTorch tensors), 8-byte aligned; with
+ * BMM_FLAG_HOST_OPERANDS they are page-locked host pointers instead.  A and B
+ * are read only.  C must not overlap A, B or the workspace.  The library owns
+ * only its internal caches (a transposition scratch buffer per device, plans),
+ * released by bmm_finalize().
+ *
+ * ASYNCHRONY.  Calls enqueue work on `hip_stream` (a hipStream_t; NULL = the
+ * default stream) and return without waiting, except where noted.  The return
+ * value reports argument and launch errors; faults inside kernels surface at
+ * the caller's next synchronization.
+ *
+ * ERRORS.  Functions return a bmm_status; nothing throws or aborts across this
+ * interface.  bmm_last_error() returns a thread-local message for the last
+ * failure.
+ */
+#ifndef BMM_H
+#define BMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  BMM_OK = 0,
+  BMM_E_INVAL = -1,       /* bad size, pitch, pointer, alignment or overlap */
+  BMM_E_UNSUPPORTED = -2, /* valid request this build cannot do (e.g. Strassen sizes) */
+  BMM_E_WORKSPACE = -3,   /* workspace missing or too small */
+  BMM_E_NOMEM = -4,       /* a library-owned allocation failed */
+  BMM_E_DEVICE = -5       /* a HIP runtime error; message in bmm_last_error() */
+} bmm_status;
+
+typedef enum { BMM_GF2 = 0, BMM_BOOLEAN = 1 } bmm_semiring;
+
+/* Leaf kernels for the cubic product. */
+typedef enum {
+  BMM_LEAF_AUTO = 0,   /* autotuner's choice */
+  BMM_LEAF_VALU = 1,   /* bitwise vector ALU leaf (v_bitop3_b32) */
+  BMM_LEAF_MFMA_I8 = 2 /* int8 matrix-core leaf, exact int32 counts */
+} bmm_leaf;
+
+/* Flags. */
+#define BMM_FLAG_ACCUMULATE 0x1u    /* C ^= AB (GF(2)) or C |= AB (Boolean) */
+#define BMM_FLAG_B_TRANSPOSED 0x2u  /* B is passed as B^T: n rows of k bits, pitch ldb */
+#define BMM_FLAG_ALT_BASIS_IO 0x4u  /* Strassen only: A and B are already in the
+                                       alternative basis and C is left in it (the
+                                       paper's timing convention, section 4.2) */
+#define BMM_FLAG_HOST_OPERANDS 0x8u /* A, B, C are page-locked host memory; blocks
+                                       stream through HBM (out-of-core pipeline) */
+
+typedef struct {
+  int leaf;           /* bmm_leaf; 0 = auto */
+  int tile;           /* leaf tile variant; -1 or 0 = auto (see bmm_leaf_tiles) */
+  int depth_serial;   /* Strassen levels processed one child at a time; -1 = auto */
+  int depth_parallel; /* Strassen levels processed breadth-first; -1 = auto */
+  int64_t block;      /* out-of-core block size in bits (multiple of 64); 0 = auto */
+  uint32_t flags;     /* BMM_FLAG_* */
+} bmm_options;
+
+/* Fill *opt with the defaults (everything automatic, no flags). */
+void bmm_options_init(bmm_options* opt);
+
+/* Cubic GF(2) product C = AB (or C ^= AB): C[i][k] = XOR_j A[i][j] AND B[j][k].
+ * A: m x k (pitch lda), B: k x n (pitch ldb; n x k with BMM_FLAG_B_TRANSPOSED),
+ * C: m x n (pitch ldc).  m, k, n >= 0; zero sizes are valid and do nothing
+ * (k = 0 writes C = 0 unless accumulating).  Unless B is passed transposed the
+ * library transposes it into a cached device scratch buffer (which may call
+ * hipMalloc on first use or growth; pass B^T to avoid that).
+ * Errors: BMM_E_INVAL (negative size, null pointer with nonzero size, pitch too
+ * small, C overlapping A or B), BMM_E_NOMEM, BMM_E_DEVICE. */
+int bmm_gf2(const uint64_t* A, int64_t lda, const uint64_t* B, int64_t ldb, uint64_t* C,
+            int64_t ldc, int64_t m, int64_t k, int64_t n, const bmm_options* opt,
+            void* hip_stream);
+
+/* Cubic Boolean product C = AB (or C |= AB): C[i][k] = OR_j A[i][j] AND B[j][k]
+ * (section 3.18).  Same arguments and errors as bmm_gf2. */
+int bmm_boolean(const uint64_t* A, int64_t lda, const uint64_t* B, int64_t ldb, uint64_t* C,
+                int64_t ldc, int64_t m, int64_t k, int64_t n, const bmm_options* opt,
+                void* hip_stream);
+
+/* GF(2) product by the self-inverse alternative-basis recursion with `depth`
+ * levels of 2 x 2 blocks above a cubic leaf (depth -1 = autotuned; 0 = cubic).
+ * Requires m % 2^depth == 0, k % (64 * 2^depth) == 0 and n % (64 * 2^depth) == 0,
+ * else BMM_E_UNSUPPORTED.  The workspace (device memory, >= the size from
+ * bmm_gf2_strassen_workspace for the same arguments) holds the basis-changed
+ * operands and the expanded levels; its contents on return are unspecified.
+ * With BMM_FLAG_ALT_BASIS_IO the inputs are taken as A-hat, B-hat and C-hat is
+ * returned (no basis changes).  Errors: as bmm_gf2, plus BMM_E_WORKSPACE. */
+int bmm_gf2_strassen(const uint64_t* A, int64_t lda, const uint64_t* B, int64_t ldb,
+                     uint64_t* C, int64_t ldc, int64_t m, int64_t k, int64_t n, int depth,
+                     void* workspace, size_t workspace_bytes, const bmm_options* opt,
+                     void* hip_stream);
+
+/* Workspace bytes that bmm_gf2_strassen needs for these sizes and options, and
+ * the depth split it will use (either out pointer may be NULL). */
+int bmm_gf2_strassen_workspace(int64_t m, int64_t k, int64_t n, int depth,
+                               const bmm_options* opt, size_t* bytes_out,
+                               int* depth_serial_out, int* depth_parallel_out);
+
+/* One independent product of a batch. */
+typedef struct {
+  int semiring;           /* bmm_semiring */
+  int64_t m, k, n;
+  const uint64_t* A;      /* m x k, pitch lda */
+  const uint64_t* B;      /* k x n, pitch ldb; or n x k if b_transposed */
+  uint64_t* C;            /* m x n, pitch ldc */
+  int64_t lda, ldb, ldc;
+  int b_transposed;
+} bmm_problem;
+
+/* Many independent products of uneven sizes in one persistent launch
+ * (workgroups pull tiles from a device-side queue).  `problems` is a host
+ * array.  Operands not given transposed are transposed into library scratch
+ * first.  Equivalent to bmm_batched_plan_create + launch + destroy. */
+int bmm_batched(const bmm_problem* problems, int64_t count, const bmm_options* opt,
+                void* hip_stream);
+
+/* A reusable batched plan: the problem table lives on the device, so a launch
+ * is a fixed sequence of kernels that a caller may capture into a hipGraph and
+ * replay.  All problems must have b_transposed set.  plan_create allocates
+ * device memory (hipMalloc) and synchronizes; plan_launch only enqueues. */
+int bmm_batched_plan_create(const bmm_problem* problems, int64_t count,
+                            const bmm_options* opt, void** plan_out);
+int bmm_batched_plan_launch(void* plan, void* hip_stream);
+void bmm_batched_plan_destroy(void* plan);
+
+/* Out-of-core product of page-locked host matrices (sections 3.3, 3.16, 3.18):
+ * C = AB over `semiring` with A, B, C in host memory allocated by hipHostMalloc
+ * (else BMM_E_INVAL).  b x b blocks (block bits, a multiple of 64; 0 = option
+ * or 2^17) stream through two HBM slots with asynchronous copies on their own
+ * streams, overlapped with the leaf; finished C blocks download while the next
+ * block computes.  Synchronous: returns after C is complete; *seconds_out (if
+ * not NULL) receives the wall time.  Allocates and frees its HBM buffers. */
+int bmm_ooc(int semiring, const uint64_t* A, int64_t lda, const uint64_t* B, int64_t ldb,
+            uint64_t* C, int64_t ldc, int64_t m, int64_t k, int64_t n, int64_t block,
+            const bmm_options* opt, double* seconds_out);
+
+/* Stage entry points of the recursion (for kernel-by-kernel checks and for
+ * callers that build their own schedules).  All enqueue on hip_stream.
+ *
+ * bmm_transpose: dst (cols x rows bits, pitch ldd) = src^T (src rows x cols bits). */
+int bmm_transpose(const uint64_t* src, int64_t lds, uint64_t* dst, int64_t ldd, int64_t rows,
+                  int64_t cols, void* hip_stream);
+/* bmm_basis_change: in place on a rows x (64 * row_words) matrix, the 2 x 2
+ * basis change of the self-inverse design at the top `depth` levels:
+ * inverse = 0 applies phi (eq. mb-fwdbasisrecurrence), 1 applies chi
+ * (eq. mb-revbasisrecurrence).  rows and row_words must be divisible by 2^depth. */
+int bmm_basis_change(uint64_t* X, int64_t ld, int64_t rows, int64_t row_words, int depth,
+                     int inverse, void* hip_stream);
+/* bmm_expand: one level (levels = 1) or two merged levels (levels = 2) of the
+ * linear combinations of eq. mb-tsrecurrence for `parents` matrices of rows x
+ * (64 * words) (parent p at src + p * strideP, pitch ldp).  side 0 = left
+ * operand (alpha), 1 = right operand stored transposed (beta).  Children are
+ * written compactly to dst: 7^levels per parent, in order. */
+int bmm_expand(int side, int levels, const uint64_t* src, int64_t ldp, int64_t strideP,
+               uint64_t* dst, int64_t rows, int64_t words, int64_t parents, void* hip_stream);
+/* bmm_compress: the inverse step for products (eq. mb-qrecurrence): 7^levels
+ * compact children per parent combine into the parents' quadrants. */
+int bmm_compress(int levels, const uint64_t* src, uint64_t* dst, int64_t ldp, int64_t strideP,
+                 int64_t rows, int64_t words, int64_t parents, void* hip_stream);
+
+/* Number of tile variants of a leaf (valid values of bmm_options.tile are
+ * 1..count; 0 = auto), and the C tile (rows x columns) of a variant. */
+int bmm_leaf_tiles(int leaf, int* count_out);
+int bmm_leaf_tile_shape(int leaf, int tile, int* rows_out, int* cols_out);
+
+/* Autotuner: time the candidate leaf kernels / Strassen splits for a shape on
+ * the current device (synchronizes; allocates scratch) and remember the best in
+ * the in-process table that BMM_LEAF_AUTO and depth -1 consult.  The table can
+ * be saved and loaded as text. */
+int bmm_autotune_cubic(int semiring, int64_t m, int64_t k, int64_t n, int* leaf_out,
+                       int* tile_out, double* seconds_out);
+int bmm_autotune_set(int semiring, int64_t m, int64_t k, int64_t n, int leaf, int tile);
+int bmm_autotune_save(const char* path);
+int bmm_autotune_load(const char* path);
+
+const char* bmm_status_string(int status);
+const char* bmm_last_error(void);
+const char* bmm_version(void);
+/* Free library-owned device memory (scratch, plans' caches).  Not thread-safe
+ * against concurrent calls on other threads. */
+void bmm_finalize(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BMM_H */

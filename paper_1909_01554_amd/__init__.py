@@ -1,0 +1,321 @@
+"""Python binding of libbmm.so: exact packed bit-matrix products on MI355X.
+
+Argument marshalling only: every step of every product runs in the HIP
+kernels of ``libbmm.so``.  Importing this package raises if the library is
+not built; there is no CPU fallback.
+
+Matrices are torch.int64 CUDA tensors holding packed rows (shape rows x ld,
+bit j of a row at bit j % 64 of word j // 64).  Calls are asynchronous on the
+tensor device's current stream.  The names mirror the C entry points declared
+in ``include/bmm.h``.
+"""
+import ctypes
+import os
+
+from . import build as _build
+
+__all__ = [
+    "BmmError", "Options", "GF2", "BOOLEAN", "LEAF_AUTO", "LEAF_VALU", "LEAF_MFMA_I8",
+    "FLAG_ACCUMULATE", "FLAG_B_TRANSPOSED", "FLAG_ALT_BASIS_IO", "FLAG_HOST_OPERANDS",
+    "words", "bmm_gf2", "bmm_boolean", "bmm_gf2_strassen", "bmm_gf2_strassen_workspace",
+    "bmm_batched", "BatchedPlan", "bmm_transpose", "bmm_basis_change", "bmm_expand",
+    "bmm_compress", "bmm_ooc", "bmm_autotune_cubic", "bmm_autotune_set", "bmm_autotune_save",
+    "bmm_autotune_load", "bmm_leaf_tiles", "bmm_leaf_tile_shape", "bmm_version",
+    "bmm_finalize", "library_path",
+]
+
+GF2, BOOLEAN = 0, 1
+LEAF_AUTO, LEAF_VALU, LEAF_MFMA_I8 = 0, 1, 2
+FLAG_ACCUMULATE = 0x1
+FLAG_B_TRANSPOSED = 0x2
+FLAG_ALT_BASIS_IO = 0x4
+FLAG_HOST_OPERANDS = 0x8
+
+_STATUS = {0: "ok", -1: "invalid argument", -2: "unsupported", -3: "workspace too small",
+           -4: "out of memory", -5: "device error"}
+
+
+class BmmError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{_STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+def library_path():
+    return _build.SO
+
+
+if not os.path.exists(_build.SO):
+    raise ImportError(f"{_build.SO} is not built; run __graft_entry__.build() "
+                      "(python -m paper_1909_01554_amd.build)")
+
+_lib = ctypes.CDLL(_build.SO)
+_i64 = ctypes.c_int64
+_vp = ctypes.c_void_p
+_int = ctypes.c_int
+
+
+class Options(ctypes.Structure):
+    """bmm_options: leaf, tile, depth_serial, depth_parallel, block, flags."""
+    _fields_ = [("leaf", _int), ("tile", _int), ("depth_serial", _int),
+                ("depth_parallel", _int), ("block", _i64), ("flags", ctypes.c_uint32)]
+
+    def __init__(self, leaf=LEAF_AUTO, tile=0, depth_serial=-1, depth_parallel=-1, block=0,
+                 flags=0):
+        super().__init__(leaf, tile, depth_serial, depth_parallel, block, flags)
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("semiring", _int), ("m", _i64), ("k", _i64), ("n", _i64), ("A", _vp),
+                ("B", _vp), ("C", _vp), ("lda", _i64), ("ldb", _i64), ("ldc", _i64),
+                ("b_transposed", _int)]
+
+
+def _sig(name, args, res=_int):
+    f = getattr(_lib, name)
+    f.argtypes = args
+    f.restype = res
+    return f
+
+
+_prod_args = [_vp, _i64, _vp, _i64, _vp, _i64, _i64, _i64, _i64, ctypes.POINTER(Options), _vp]
+_c_gf2 = _sig("bmm_gf2", _prod_args)
+_c_boolean = _sig("bmm_boolean", _prod_args)
+_c_strassen = _sig("bmm_gf2_strassen", [_vp, _i64, _vp, _i64, _vp, _i64, _i64, _i64, _i64, _int,
+                                        _vp, ctypes.c_size_t, ctypes.POINTER(Options), _vp])
+_c_strassen_ws = _sig("bmm_gf2_strassen_workspace",
+                      [_i64, _i64, _i64, _int, ctypes.POINTER(Options),
+                       ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(_int),
+                       ctypes.POINTER(_int)])
+_c_batched = _sig("bmm_batched", [ctypes.POINTER(Problem), _i64, ctypes.POINTER(Options), _vp])
+_c_plan_create = _sig("bmm_batched_plan_create", [ctypes.POINTER(Problem), _i64,
+                                                  ctypes.POINTER(Options), ctypes.POINTER(_vp)])
+_c_plan_launch = _sig("bmm_batched_plan_launch", [_vp, _vp])
+_c_plan_destroy = _sig("bmm_batched_plan_destroy", [_vp], None)
+_c_transpose = _sig("bmm_transpose", [_vp, _i64, _vp, _i64, _i64, _i64, _vp])
+_c_basis = _sig("bmm_basis_change", [_vp, _i64, _i64, _i64, _int, _int, _vp])
+_c_expand = _sig("bmm_expand", [_int, _int, _vp, _i64, _i64, _vp, _i64, _i64, _i64, _vp])
+_c_compress = _sig("bmm_compress", [_int, _vp, _vp, _i64, _i64, _i64, _i64, _i64, _vp])
+_c_ooc = _sig("bmm_ooc", [_int, _vp, _i64, _vp, _i64, _vp, _i64, _i64, _i64, _i64, _i64,
+                          ctypes.POINTER(Options), ctypes.POINTER(ctypes.c_double)])
+_c_tune = _sig("bmm_autotune_cubic", [_int, _i64, _i64, _i64, ctypes.POINTER(_int),
+                                      ctypes.POINTER(_int), ctypes.POINTER(ctypes.c_double)])
+_c_tune_set = _sig("bmm_autotune_set", [_int, _i64, _i64, _i64, _int, _int])
+_c_tune_save = _sig("bmm_autotune_save", [ctypes.c_char_p])
+_c_tune_load = _sig("bmm_autotune_load", [ctypes.c_char_p])
+_c_tiles = _sig("bmm_leaf_tiles", [_int, ctypes.POINTER(_int)])
+_c_tile_shape = _sig("bmm_leaf_tile_shape", [_int, _int, ctypes.POINTER(_int),
+                                             ctypes.POINTER(_int)])
+_c_last_error = _sig("bmm_last_error", [], ctypes.c_char_p)
+_c_version = _sig("bmm_version", [], ctypes.c_char_p)
+_c_finalize = _sig("bmm_finalize", [], None)
+
+
+def _check(rc):
+    if rc != 0:
+        raise BmmError(rc, _c_last_error().decode(errors="replace"))
+
+
+def words(bits):
+    return (int(bits) + 63) // 64
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(t, stream):
+    if stream is not None:
+        return ctypes.c_void_p(int(stream))
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _ld(t):
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError("matrices must be 2-D with contiguous rows")
+    return t.stride(0)
+
+
+def _opts(options, flags):
+    o = Options() if options is None else Options(options.leaf, options.tile,
+                                                  options.depth_serial,
+                                                  options.depth_parallel, options.block,
+                                                  options.flags)
+    o.flags |= flags
+    return o
+
+
+def _product(fn, A, B, C, m, k, n, options, flags, stream):
+    o = _opts(options, flags)
+    _check(fn(_ptr(A), _ld(A), _ptr(B), _ld(B), _ptr(C), _ld(C), m, k, n, ctypes.byref(o),
+              _stream(C, stream)))
+    return C
+
+
+def bmm_gf2(A, B, C, m, k, n, options=None, b_transposed=False, accumulate=False, stream=None):
+    """C = AB (or C ^= AB) over GF(2) by the cubic method."""
+    flags = (FLAG_B_TRANSPOSED if b_transposed else 0) | (FLAG_ACCUMULATE if accumulate else 0)
+    return _product(_c_gf2, A, B, C, m, k, n, options, flags, stream)
+
+
+def bmm_boolean(A, B, C, m, k, n, options=None, b_transposed=False, accumulate=False,
+                stream=None):
+    """C = AB (or C |= AB) over the Boolean algebra by the cubic method."""
+    flags = (FLAG_B_TRANSPOSED if b_transposed else 0) | (FLAG_ACCUMULATE if accumulate else 0)
+    return _product(_c_boolean, A, B, C, m, k, n, options, flags, stream)
+
+
+def bmm_gf2_strassen_workspace(m, k, n, depth=-1, options=None, alt_basis_io=False):
+    """(bytes, depth_serial, depth_parallel) of the Strassen product's workspace."""
+    o = _opts(options, FLAG_ALT_BASIS_IO if alt_basis_io else 0)
+    nbytes = ctypes.c_size_t(0)
+    ds = _int(0)
+    dp = _int(0)
+    _check(_c_strassen_ws(m, k, n, depth, ctypes.byref(o), ctypes.byref(nbytes),
+                          ctypes.byref(ds), ctypes.byref(dp)))
+    return nbytes.value, ds.value, dp.value
+
+
+def bmm_gf2_strassen(A, B, C, m, k, n, workspace, depth=-1, options=None, b_transposed=False,
+                     alt_basis_io=False, stream=None):
+    """C = AB over GF(2) by the self-inverse alternative-basis recursion."""
+    o = _opts(options, (FLAG_B_TRANSPOSED if b_transposed else 0)
+              | (FLAG_ALT_BASIS_IO if alt_basis_io else 0))
+    nbytes = workspace.numel() * workspace.element_size()
+    _check(_c_strassen(_ptr(A), _ld(A), _ptr(B), _ld(B), _ptr(C), _ld(C), m, k, n, depth,
+                       _ptr(workspace), nbytes, ctypes.byref(o), _stream(C, stream)))
+    return C
+
+
+def _problems(problems):
+    arr = (Problem * len(problems))()
+    for i, p in enumerate(problems):
+        arr[i] = Problem(p["semiring"], p["m"], p["k"], p["n"], p["A"].data_ptr(),
+                         p["B"].data_ptr(), p["C"].data_ptr(), _ld(p["A"]), _ld(p["B"]),
+                         _ld(p["C"]), 1 if p.get("b_transposed") else 0)
+    return arr
+
+
+def bmm_batched(problems, options=None, stream=None):
+    """Independent products (dicts with semiring, m, k, n, A, B, C[, b_transposed])
+    in one persistent launch."""
+    if not problems:
+        return
+    arr = _problems(problems)
+    o = _opts(options, 0)
+    _check(_c_batched(arr, len(problems), ctypes.byref(o),
+                      _stream(problems[0]["C"], stream)))
+
+
+class BatchedPlan:
+    """bmm_batched_plan_*: a device-resident problem table for repeated launches
+    (capturable into a HIP graph).  Every problem must be b_transposed."""
+
+    def __init__(self, problems, options=None):
+        self._keep = problems
+        arr = _problems(problems)
+        o = _opts(options, 0)
+        h = _vp()
+        _check(_c_plan_create(arr, len(problems), ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+
+    def launch(self, stream=None):
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream().cuda_stream
+        _check(_c_plan_launch(self._h, ctypes.c_void_p(int(stream))))
+
+    def destroy(self):
+        if self._h:
+            _c_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def bmm_transpose(src, dst, rows, cols, stream=None):
+    _check(_c_transpose(_ptr(src), _ld(src), _ptr(dst), _ld(dst), rows, cols,
+                        _stream(dst, stream)))
+    return dst
+
+
+def bmm_basis_change(X, rows, row_words, depth, inverse=False, stream=None):
+    _check(_c_basis(_ptr(X), _ld(X), rows, row_words, depth, 1 if inverse else 0,
+                    _stream(X, stream)))
+    return X
+
+
+def bmm_expand(side, levels, src, ldp, stride_p, dst, rows, words_, parents, stream=None):
+    _check(_c_expand(side, levels, _ptr(src), ldp, stride_p, _ptr(dst), rows, words_, parents,
+                     _stream(dst, stream)))
+    return dst
+
+
+def bmm_compress(levels, src, dst, ldp, stride_p, rows, words_, parents, stream=None):
+    _check(_c_compress(levels, _ptr(src), _ptr(dst), ldp, stride_p, rows, words_, parents,
+                       _stream(dst, stream)))
+    return dst
+
+
+def bmm_ooc(semiring, A, B, C, m, k, n, block=0, options=None):
+    """Out-of-core product of page-locked host matrices (numpy or pinned torch
+    CPU tensors) streamed through HBM.  Synchronous; returns the seconds spent."""
+    def hptr(t):
+        if hasattr(t, "data_ptr"):
+            return ctypes.c_void_p(t.data_ptr()), t.stride(0)
+        return ctypes.c_void_p(t.ctypes.data), t.strides[0] // 8
+    o = _opts(options, FLAG_HOST_OPERANDS)
+    a, lda = hptr(A)
+    b, ldb = hptr(B)
+    c, ldc = hptr(C)
+    secs = ctypes.c_double(0.0)
+    _check(_c_ooc(semiring, a, lda, b, ldb, c, ldc, m, k, n, block, ctypes.byref(o),
+                  ctypes.byref(secs)))
+    return secs.value
+
+
+def bmm_autotune_cubic(semiring, m, k, n):
+    leaf = _int(0)
+    tile = _int(0)
+    secs = ctypes.c_double(0.0)
+    _check(_c_tune(semiring, m, k, n, ctypes.byref(leaf), ctypes.byref(tile),
+                   ctypes.byref(secs)))
+    return leaf.value, tile.value, secs.value
+
+
+def bmm_autotune_set(semiring, m, k, n, leaf, tile):
+    _check(_c_tune_set(semiring, m, k, n, leaf, tile))
+
+
+def bmm_autotune_save(path):
+    _check(_c_tune_save(path.encode()))
+
+
+def bmm_autotune_load(path):
+    _check(_c_tune_load(path.encode()))
+
+
+def bmm_leaf_tiles(leaf):
+    c = _int(0)
+    _check(_c_tiles(leaf, ctypes.byref(c)))
+    return c.value
+
+
+def bmm_leaf_tile_shape(leaf, tile):
+    r = _int(0)
+    c = _int(0)
+    _check(_c_tile_shape(leaf, tile, ctypes.byref(r), ctypes.byref(c)))
+    return r.value, c.value
+
+
+def bmm_version():
+    return _c_version().decode()
+
+
+def bmm_finalize():
+    _c_finalize()

@@ -1,0 +1,682 @@
+// C-ABI entry points: argument checks, plans and launch sequences.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/bmm.h"
+#include "bmm_internal.h"
+
+using namespace bmm;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+}  // namespace
+
+namespace bmm {
+int set_error(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+}  // namespace bmm
+
+namespace {
+
+#define fail bmm::set_error
+
+int check_hip(hipError_t e, const char* what) {
+  if (e == hipSuccess) return BMM_OK;
+  return fail(BMM_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define BMM_TRY(expr)                 \
+  do {                                \
+    int _rc = (expr);                 \
+    if (_rc != BMM_OK) return _rc;    \
+  } while (0)
+
+#define HIP_TRY(expr, what) BMM_TRY(check_hip((expr), (what)))
+
+inline int64_t words_of(int64_t bits) { return (bits + 63) / 64; }
+
+struct Extent {
+  uintptr_t lo, hi;
+};
+
+Extent extent(const void* p, int64_t rows, int64_t ld, int64_t row_words) {
+  const uintptr_t lo = reinterpret_cast<uintptr_t>(p);
+  if (rows <= 0 || row_words <= 0) return {lo, lo};
+  return {lo, lo + (uintptr_t)(((rows - 1) * ld + row_words) * 8)};
+}
+
+bool overlaps(Extent a, Extent b) { return a.lo < b.hi && b.lo < a.hi; }
+
+bmm_options defaults() {
+  bmm_options o;
+  bmm_options_init(&o);
+  return o;
+}
+
+// ---- library-owned scratch (per device), used for B^T in the cubic calls ----
+std::mutex g_mu;
+std::map<int, std::pair<void*, size_t>> g_scratch;
+
+int scratch(size_t bytes, void** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+  std::lock_guard<std::mutex> lock(g_mu);
+  auto& slot = g_scratch[dev];
+  if (slot.second < bytes) {
+    if (slot.first) {
+      // earlier work may still read the old buffer
+      HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
+      HIP_TRY(hipFree(slot.first), "hipFree");
+      slot = {nullptr, 0};
+    }
+    size_t want = std::max(bytes, (size_t)1 << 20);
+    void* p = nullptr;
+    if (hipMalloc(&p, want) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return fail(BMM_E_NOMEM, "scratch allocation of %zu bytes failed", want);
+    }
+    slot = {p, want};
+  }
+  *out = slot.first;
+  return BMM_OK;
+}
+
+// ---- autotune table ----
+struct TuneKey {
+  int semiring;
+  int64_t m, k, n;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(semiring, m, k, n) < std::tie(o.semiring, o.m, o.k, o.n);
+  }
+};
+std::map<TuneKey, std::pair<int, int>> g_tune;
+
+void pick_leaf(int semiring, int64_t m, int64_t k, int64_t n, const bmm_options& o, int* leaf,
+               int* tile) {
+  *leaf = o.leaf;
+  *tile = o.tile;
+  if (*leaf == BMM_LEAF_AUTO || *tile <= 0) {
+    std::lock_guard<std::mutex> lock(g_mu);
+    auto it = g_tune.find({semiring, m, k, n});
+    if (it != g_tune.end()) {
+      if (*leaf == BMM_LEAF_AUTO) *leaf = it->second.first;
+      if (*tile <= 0 && *leaf == it->second.first) *tile = it->second.second;
+    }
+  }
+  if (*leaf == BMM_LEAF_AUTO) *leaf = BMM_LEAF_MFMA_I8;
+  if (*tile <= 0) {
+    // default MFMA tile: 128 x 64 per wave; small problems use 64 x 64 to fill the chip
+    *tile = 1;
+    if (*leaf == BMM_LEAF_MFMA_I8 && m * n < (int64_t)8192 * 8192) *tile = 2;
+  }
+}
+
+int run_leaf(int semiring, int leaf, int tile, const LeafBatch& p, hipStream_t s) {
+  hipError_t e;
+  if (leaf == BMM_LEAF_VALU) {
+    e = launch_leaf_valu(semiring, p, tile - 1, s);
+  } else if (leaf == BMM_LEAF_MFMA_I8) {
+    e = launch_leaf_mfma(semiring, p, tile - 1, s);
+  } else {
+    return fail(BMM_E_INVAL, "unknown leaf %d", leaf);
+  }
+  return check_hip(e, "leaf launch");
+}
+
+int validate_product(const uint64_t* A, int64_t lda, const uint64_t* B, int64_t ldb,
+                     const uint64_t* C, int64_t ldc, int64_t m, int64_t k, int64_t n,
+                     bool b_t) {
+  if (m < 0 || k < 0 || n < 0) return fail(BMM_E_INVAL, "negative size (m=%ld k=%ld n=%ld)", (long)m, (long)k, (long)n);
+  if (m == 0 || n == 0) return BMM_OK;
+  const int64_t kw = words_of(k), nw = words_of(n);
+  if (!C) return fail(BMM_E_INVAL, "C is null");
+  if (ldc < nw) return fail(BMM_E_INVAL, "ldc=%ld < %ld words", (long)ldc, (long)nw);
+  if ((reinterpret_cast<uintptr_t>(C) & 7) != 0) return fail(BMM_E_INVAL, "C not 8-byte aligned");
+  if (k == 0) return BMM_OK;
+  if (!A || !B) return fail(BMM_E_INVAL, "A or B is null");
+  if (((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B)) & 7) != 0)
+    return fail(BMM_E_INVAL, "A or B not 8-byte aligned");
+  if (lda < kw) return fail(BMM_E_INVAL, "lda=%ld < %ld words", (long)lda, (long)kw);
+  if (b_t ? ldb < kw : ldb < nw) return fail(BMM_E_INVAL, "ldb=%ld too small", (long)ldb);
+  const Extent ec = extent(C, m, ldc, nw);
+  if (overlaps(ec, extent(A, m, lda, kw))) return fail(BMM_E_INVAL, "C overlaps A");
+  if (overlaps(ec, b_t ? extent(B, n, ldb, kw) : extent(B, k, ldb, nw)))
+    return fail(BMM_E_INVAL, "C overlaps B");
+  return BMM_OK;
+}
+
+int cubic(int semiring, const uint64_t* A, int64_t lda, const uint64_t* B, int64_t ldb,
+          uint64_t* C, int64_t ldc, int64_t m, int64_t k, int64_t n, const bmm_options* opt,
+          void* stream) {
+  const bmm_options o = opt ? *opt : defaults();
+  if (o.flags & BMM_FLAG_HOST_OPERANDS)
+    return fail(BMM_E_UNSUPPORTED, "host operands: use the out-of-core entry (bmm_ooc)");
+  const bool b_t = (o.flags & BMM_FLAG_B_TRANSPOSED) != 0;
+  BMM_TRY(validate_product(A, lda, B, ldb, C, ldc, m, k, n, b_t));
+  if (m == 0 || n == 0) return BMM_OK;
+  hipStream_t s = (hipStream_t)stream;
+  const bool acc = (o.flags & BMM_FLAG_ACCUMULATE) != 0;
+  const int64_t kw = words_of(k);
+  if (k == 0) {
+    if (!acc) HIP_TRY(launch_zero(C, ldc, m, words_of(n), s), "zero");
+    return BMM_OK;
+  }
+  const uint64_t* BT = B;
+  int64_t ldbt = ldb;
+  if (!b_t) {
+    void* buf = nullptr;
+    BMM_TRY(scratch((size_t)n * kw * 8, &buf));
+    HIP_TRY(launch_transpose(B, ldb, 0, (uint64_t*)buf, kw, 0, k, n, 1, s), "transpose");
+    BT = (const uint64_t*)buf;
+    ldbt = kw;
+  }
+  int leaf, tile;
+  pick_leaf(semiring, m, k, n, o, &leaf, &tile);
+  LeafBatch p{A, lda, 0, BT, ldbt, 0, C, ldc, 0, m, k, n, 1, acc ? 1 : 0};
+  return run_leaf(semiring, leaf, tile, p, s);
+}
+
+// ---- Strassen plan ----
+struct Level {
+  size_t T, S, Q;  // byte offsets in the workspace
+};
+
+struct StrassenPlan {
+  int depth = 0, ds = 0, dp = 0;
+  int64_t m = 0, kw = 0, n = 0, nw = 0;
+  size_t ahat = 0, bhat = 0;
+  std::vector<Level> serial;         // levels 1..ds (index l-1)
+  std::vector<int> psteps;           // parallel step sizes (1 or 2 levels)
+  std::vector<Level> par;            // buffers after each parallel step
+  size_t bytes = 0;
+};
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int make_plan(int64_t m, int64_t k, int64_t n, int depth, const bmm_options& o, bool alt_io,
+              StrassenPlan* plan) {
+  if (m < 0 || k < 0 || n < 0) return fail(BMM_E_INVAL, "negative size");
+  if (depth < -1 || depth > 12) return fail(BMM_E_INVAL, "depth %d out of range", depth);
+  StrassenPlan P;
+  P.m = m;
+  P.kw = words_of(k);
+  P.n = n;
+  P.nw = words_of(n);
+  if (depth == -1) {
+    // largest depth keeping every leaf dimension >= 4096 bits (at most 8 levels)
+    depth = 0;
+    while (depth < 8) {
+      const int d = depth + 1;
+      const int64_t u = (int64_t)1 << d;
+      if (m % u || k % (64 * u) || n % (64 * u)) break;
+      if (m / u < 4096 || k / u < 4096 || n / u < 4096) break;
+      depth = d;
+    }
+  }
+  const int64_t u = (int64_t)1 << depth;
+  if (m % u || k % (64 * u) || n % (64 * u))
+    return fail(BMM_E_UNSUPPORTED,
+                "Strassen depth %d needs m %% 2^d == 0 and k, n %% (64 * 2^d) == 0", depth);
+  P.depth = depth;
+  int dp = o.depth_parallel, ds = o.depth_serial;
+  if (dp < 0 && ds < 0) {
+    dp = std::min(depth, 4);
+    ds = depth - dp;
+  } else if (dp < 0) {
+    ds = std::min(ds, depth);
+    dp = depth - ds;
+  } else if (ds < 0) {
+    dp = std::min(dp, depth);
+    ds = depth - dp;
+  }
+  if (ds + dp != depth || ds < 0 || dp < 0)
+    return fail(BMM_E_INVAL, "depth_serial %d + depth_parallel %d != depth %d", ds, dp, depth);
+  P.ds = ds;
+  P.dp = dp;
+  size_t off = 0;
+  if (!alt_io) {
+    P.ahat = off;
+    off = align_up(off + (size_t)m * P.kw * 8);
+  }
+  P.bhat = off;
+  off = align_up(off + (size_t)n * P.kw * 8);
+  for (int l = 1; l <= ds; ++l) {
+    const int64_t M = m >> l, KW = P.kw >> l, N = n >> l, NW = P.nw >> l;
+    Level L;
+    L.T = off;
+    off = align_up(off + (size_t)7 * M * KW * 8);
+    L.S = off;
+    off = align_up(off + (size_t)7 * N * KW * 8);
+    L.Q = off;
+    off = align_up(off + (size_t)7 * M * NW * 8);
+    P.serial.push_back(L);
+  }
+  int left = dp, lvl = ds;
+  int64_t inst = 1;
+  while (left > 0) {
+    const int step = left >= 2 ? 2 : 1;
+    lvl += step;
+    left -= step;
+    inst *= step == 2 ? 49 : 7;
+    const int64_t M = m >> lvl, KW = P.kw >> lvl, N = n >> lvl, NW = P.nw >> lvl;
+    Level L;
+    L.T = off;
+    off = align_up(off + (size_t)inst * M * KW * 8);
+    L.S = off;
+    off = align_up(off + (size_t)inst * N * KW * 8);
+    L.Q = off;
+    off = align_up(off + (size_t)inst * M * NW * 8);
+    P.psteps.push_back(step);
+    P.par.push_back(L);
+  }
+  P.bytes = std::max(off, (size_t)256);
+  *plan = P;
+  return BMM_OK;
+}
+
+struct StrassenRun {
+  const StrassenPlan* P;
+  char* ws;
+  int leaf, tile;
+  hipStream_t s;
+
+  uint64_t* at(size_t off) const { return reinterpret_cast<uint64_t*>(ws + off); }
+
+  int parallel(int level, const uint64_t* T, int64_t ldT, const uint64_t* S, int64_t ldS,
+               uint64_t* Q, int64_t ldQ) const {
+    const StrassenPlan& p = *P;
+    const uint64_t* curT = T;
+    const uint64_t* curS = S;
+    int64_t pitchT = ldT, pitchS = ldS, strideT = 0, strideS = 0;
+    int64_t inst = 1;
+    int lvl = level;
+    for (size_t i = 0; i < p.psteps.size(); ++i) {
+      const int step = p.psteps[i];
+      const int64_t M = p.m >> lvl, KW = p.kw >> lvl, N = p.n >> lvl;
+      const Level& L = p.par[i];
+      if (step == 2) {
+        HIP_TRY(launch_expand2(0, curT, pitchT, strideT, at(L.T), M, KW, inst, s), "expand2 T");
+        HIP_TRY(launch_expand2(1, curS, pitchS, strideS, at(L.S), N, KW, inst, s), "expand2 S");
+      } else {
+        HIP_TRY(launch_expand(0, curT, pitchT, strideT, at(L.T), M, KW, inst, s), "expand T");
+        HIP_TRY(launch_expand(1, curS, pitchS, strideS, at(L.S), N, KW, inst, s), "expand S");
+      }
+      lvl += step;
+      inst *= step == 2 ? 49 : 7;
+      curT = at(L.T);
+      curS = at(L.S);
+      pitchT = pitchS = p.kw >> lvl;
+      strideT = (p.m >> lvl) * pitchT;
+      strideS = (p.n >> lvl) * pitchS;
+    }
+    // leaf products of all instances at the bottom level
+    const int64_t M = p.m >> lvl, N = p.n >> lvl, NW = p.nw >> lvl;
+    uint64_t* leafQ = p.par.empty() ? Q : at(p.par.back().Q);
+    const int64_t ldLQ = p.par.empty() ? ldQ : NW;
+    LeafBatch lb{curT, pitchT, strideT, curS, pitchS, strideS, leafQ, ldLQ, M * NW,
+                 M, (p.kw >> lvl) * 64, N, inst, 0};
+    BMM_TRY(run_leaf(BMM_GF2, leaf, tile, lb, s));
+    // compress back up
+    for (int i = (int)p.psteps.size() - 1; i >= 0; --i) {
+      const int step = p.psteps[i];
+      inst /= step == 2 ? 49 : 7;
+      lvl -= step;
+      const uint64_t* src = at(p.par[i].Q);
+      uint64_t* dst;
+      int64_t ldd, strideD;
+      if (i == 0) {
+        dst = Q;
+        ldd = ldQ;
+        strideD = 0;
+      } else {
+        dst = at(p.par[i - 1].Q);
+        ldd = p.nw >> lvl;
+        strideD = (p.m >> lvl) * ldd;
+      }
+      const int64_t M2 = p.m >> lvl, NW2 = p.nw >> lvl;
+      if (step == 2)
+        HIP_TRY(launch_compress2(src, dst, ldd, strideD, M2, NW2, inst, s), "compress2");
+      else
+        HIP_TRY(launch_compress(src, dst, ldd, strideD, M2, NW2, inst, s), "compress");
+    }
+    return BMM_OK;
+  }
+
+  int solve(int level, const uint64_t* T, int64_t ldT, const uint64_t* S, int64_t ldS,
+            uint64_t* Q, int64_t ldQ) const {
+    const StrassenPlan& p = *P;
+    if (level >= p.ds) return parallel(level, T, ldT, S, ldS, Q, ldQ);
+    const int64_t M = p.m >> level, KW = p.kw >> level, N = p.n >> level, NW = p.nw >> level;
+    const Level& L = p.serial[level];
+    HIP_TRY(launch_expand(0, T, ldT, 0, at(L.T), M, KW, 1, s), "serial expand T");
+    HIP_TRY(launch_expand(1, S, ldS, 0, at(L.S), N, KW, 1, s), "serial expand S");
+    const int64_t cT = (M / 2) * (KW / 2), cS = (N / 2) * (KW / 2), cQ = (M / 2) * (NW / 2);
+    for (int h = 0; h < 7; ++h)
+      BMM_TRY(solve(level + 1, at(L.T) + h * cT, KW / 2, at(L.S) + h * cS, KW / 2,
+                    at(L.Q) + h * cQ, NW / 2));
+    HIP_TRY(launch_compress(at(L.Q), Q, ldQ, 0, M, NW, 1, s), "serial compress");
+    return BMM_OK;
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+void bmm_options_init(bmm_options* opt) {
+  if (!opt) return;
+  opt->leaf = BMM_LEAF_AUTO;
+  opt->tile = 0;
+  opt->depth_serial = -1;
+  opt->depth_parallel = -1;
+  opt->block = 0;
+  opt->flags = 0;
+}
+
+int bmm_gf2(const uint64_t* A, int64_t lda, const uint64_t* B, int64_t ldb, uint64_t* C,
+            int64_t ldc, int64_t m, int64_t k, int64_t n, const bmm_options* opt,
+            void* hip_stream) {
+  return cubic(BMM_GF2, A, lda, B, ldb, C, ldc, m, k, n, opt, hip_stream);
+}
+
+int bmm_boolean(const uint64_t* A, int64_t lda, const uint64_t* B, int64_t ldb, uint64_t* C,
+                int64_t ldc, int64_t m, int64_t k, int64_t n, const bmm_options* opt,
+                void* hip_stream) {
+  return cubic(BMM_BOOLEAN, A, lda, B, ldb, C, ldc, m, k, n, opt, hip_stream);
+}
+
+int bmm_gf2_strassen_workspace(int64_t m, int64_t k, int64_t n, int depth,
+                               const bmm_options* opt, size_t* bytes_out,
+                               int* depth_serial_out, int* depth_parallel_out) {
+  const bmm_options o = opt ? *opt : defaults();
+  StrassenPlan P;
+  BMM_TRY(make_plan(m, k, n, depth, o, (o.flags & BMM_FLAG_ALT_BASIS_IO) != 0, &P));
+  if (bytes_out) *bytes_out = P.bytes;
+  if (depth_serial_out) *depth_serial_out = P.ds;
+  if (depth_parallel_out) *depth_parallel_out = P.dp;
+  return BMM_OK;
+}
+
+int bmm_gf2_strassen(const uint64_t* A, int64_t lda, const uint64_t* B, int64_t ldb,
+                     uint64_t* C, int64_t ldc, int64_t m, int64_t k, int64_t n, int depth,
+                     void* workspace, size_t workspace_bytes, const bmm_options* opt,
+                     void* hip_stream) {
+  const bmm_options o = opt ? *opt : defaults();
+  if (o.flags & BMM_FLAG_HOST_OPERANDS)
+    return fail(BMM_E_UNSUPPORTED, "host operands: use the out-of-core entry (bmm_ooc)");
+  const bool b_t = (o.flags & BMM_FLAG_B_TRANSPOSED) != 0;
+  const bool alt = (o.flags & BMM_FLAG_ALT_BASIS_IO) != 0;
+  if (o.flags & BMM_FLAG_ACCUMULATE)
+    return fail(BMM_E_UNSUPPORTED, "accumulate is not supported by the Strassen product");
+  BMM_TRY(validate_product(A, lda, B, ldb, C, ldc, m, k, n, b_t));
+  StrassenPlan P;
+  BMM_TRY(make_plan(m, k, n, depth, o, alt, &P));
+  if (m == 0 || n == 0) return BMM_OK;
+  hipStream_t s = (hipStream_t)hip_stream;
+  if (k == 0) return check_hip(launch_zero(C, ldc, m, P.nw, s), "zero");
+  if (!workspace || workspace_bytes < P.bytes)
+    return fail(BMM_E_WORKSPACE, "workspace of %zu bytes needed, %zu given", P.bytes,
+                workspace_bytes);
+  if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
+    return fail(BMM_E_INVAL, "workspace must be 256-byte aligned");
+  const Extent ew{reinterpret_cast<uintptr_t>(workspace),
+                  reinterpret_cast<uintptr_t>(workspace) + P.bytes};
+  if (overlaps(ew, extent(C, m, ldc, P.nw)) || overlaps(ew, extent(A, m, lda, P.kw)) ||
+      overlaps(ew, b_t ? extent(B, n, ldb, P.kw) : extent(B, k, ldb, P.nw)))
+    return fail(BMM_E_INVAL, "workspace overlaps an operand");
+  char* ws = static_cast<char*>(workspace);
+  uint64_t* BT = reinterpret_cast<uint64_t*>(ws + P.bhat);
+  if (b_t)
+    HIP_TRY(launch_copy(B, ldb, BT, P.kw, n, P.kw, s), "copy B^T");
+  else
+    HIP_TRY(launch_transpose(B, ldb, 0, BT, P.kw, 0, k, n, 1, s), "transpose B");
+  const uint64_t* T0 = A;
+  int64_t ldT0 = lda;
+  if (!alt) {
+    uint64_t* Ah = reinterpret_cast<uint64_t*>(ws + P.ahat);
+    HIP_TRY(launch_copy(A, lda, Ah, P.kw, m, P.kw, s), "copy A");
+    HIP_TRY(launch_basis(Ah, P.kw, 0, m, P.kw, 1, P.depth, 0, s), "basis A");
+    HIP_TRY(launch_basis(BT, P.kw, 0, n, P.kw, 1, P.depth, 0, s), "basis B");
+    T0 = Ah;
+    ldT0 = P.kw;
+  }
+  int leaf, tile;
+  const int64_t u = (int64_t)1 << P.depth;
+  pick_leaf(BMM_GF2, m / u, k / u, n / u, o, &leaf, &tile);
+  StrassenRun run{&P, ws, leaf, tile, s};
+  BMM_TRY(run.solve(0, T0, ldT0, BT, P.kw, C, ldc));
+  if (!alt) HIP_TRY(launch_basis(C, ldc, 0, m, P.nw, 1, P.depth, 1, s), "basis C");
+  return BMM_OK;
+}
+
+int bmm_transpose(const uint64_t* src, int64_t lds, uint64_t* dst, int64_t ldd, int64_t rows,
+                  int64_t cols, void* hip_stream) {
+  if (rows < 0 || cols < 0) return fail(BMM_E_INVAL, "negative size");
+  if (rows == 0 || cols == 0) return BMM_OK;
+  if (!src || !dst) return fail(BMM_E_INVAL, "null pointer");
+  if (lds < words_of(cols) || ldd < words_of(rows)) return fail(BMM_E_INVAL, "pitch too small");
+  if (overlaps(extent(src, rows, lds, words_of(cols)), extent(dst, cols, ldd, words_of(rows))))
+    return fail(BMM_E_INVAL, "src and dst overlap");
+  return check_hip(launch_transpose(src, lds, 0, dst, ldd, 0, rows, cols, 1,
+                                    (hipStream_t)hip_stream),
+                   "transpose");
+}
+
+int bmm_basis_change(uint64_t* X, int64_t ld, int64_t rows, int64_t row_words, int depth,
+                     int inverse, void* hip_stream) {
+  if (rows < 0 || row_words < 0 || depth < 0 || depth > 20)
+    return fail(BMM_E_INVAL, "bad size or depth");
+  if (rows == 0 || row_words == 0 || depth == 0) return BMM_OK;
+  if (!X || ld < row_words) return fail(BMM_E_INVAL, "null pointer or pitch too small");
+  const int64_t u = (int64_t)1 << depth;
+  if (rows % u || row_words % u)
+    return fail(BMM_E_UNSUPPORTED, "rows and row words must be divisible by 2^depth");
+  return check_hip(launch_basis(X, ld, 0, rows, row_words, 1, depth, inverse ? 1 : 0,
+                                (hipStream_t)hip_stream),
+                   "basis change");
+}
+
+int bmm_expand(int side, int levels, const uint64_t* src, int64_t ldp, int64_t strideP,
+               uint64_t* dst, int64_t rows, int64_t words, int64_t parents, void* hip_stream) {
+  if ((side != 0 && side != 1) || (levels != 1 && levels != 2))
+    return fail(BMM_E_INVAL, "side must be 0/1 and levels 1/2");
+  if (rows < 0 || words < 0 || parents < 0) return fail(BMM_E_INVAL, "negative size");
+  if (rows == 0 || words == 0 || parents == 0) return BMM_OK;
+  const int64_t u = levels == 2 ? 4 : 2;
+  if (rows % u || words % u) return fail(BMM_E_UNSUPPORTED, "sizes must be divisible by %ld", (long)u);
+  if (!src || !dst || ldp < words) return fail(BMM_E_INVAL, "null pointer or pitch too small");
+  hipStream_t s = (hipStream_t)hip_stream;
+  return check_hip(levels == 2 ? launch_expand2(side, src, ldp, strideP, dst, rows, words, parents, s)
+                               : launch_expand(side, src, ldp, strideP, dst, rows, words, parents, s),
+                   "expand");
+}
+
+int bmm_compress(int levels, const uint64_t* src, uint64_t* dst, int64_t ldp, int64_t strideP,
+                 int64_t rows, int64_t words, int64_t parents, void* hip_stream) {
+  if (levels != 1 && levels != 2) return fail(BMM_E_INVAL, "levels must be 1 or 2");
+  if (rows < 0 || words < 0 || parents < 0) return fail(BMM_E_INVAL, "negative size");
+  if (rows == 0 || words == 0 || parents == 0) return BMM_OK;
+  const int64_t u = levels == 2 ? 4 : 2;
+  if (rows % u || words % u) return fail(BMM_E_UNSUPPORTED, "sizes must be divisible by %ld", (long)u);
+  if (!src || !dst || ldp < words) return fail(BMM_E_INVAL, "null pointer or pitch too small");
+  hipStream_t s = (hipStream_t)hip_stream;
+  return check_hip(levels == 2 ? launch_compress2(src, dst, ldp, strideP, rows, words, parents, s)
+                               : launch_compress(src, dst, ldp, strideP, rows, words, parents, s),
+                   "compress");
+}
+
+int bmm_leaf_tiles(int leaf, int* count_out) {
+  if (!count_out) return fail(BMM_E_INVAL, "null count_out");
+  if (leaf == BMM_LEAF_VALU) *count_out = 1;
+  else if (leaf == BMM_LEAF_MFMA_I8) *count_out = MFMA_NUM_TILES;
+  else return fail(BMM_E_INVAL, "unknown leaf %d", leaf);
+  return BMM_OK;
+}
+
+int bmm_leaf_tile_shape(int leaf, int tile, int* rows_out, int* cols_out) {
+  if (!rows_out || !cols_out) return fail(BMM_E_INVAL, "null output");
+  if (leaf == BMM_LEAF_VALU && tile == 1) {
+    *rows_out = 128;
+    *cols_out = 128;
+    return BMM_OK;
+  }
+  if (leaf == BMM_LEAF_MFMA_I8 && tile >= 1 && tile <= MFMA_NUM_TILES) {
+    *rows_out = leaf_mfma_tile_rows(tile - 1);
+    *cols_out = leaf_mfma_tile_cols(tile - 1);
+    return BMM_OK;
+  }
+  return fail(BMM_E_INVAL, "unknown leaf %d / tile %d", leaf, tile);
+}
+
+int bmm_autotune_set(int semiring, int64_t m, int64_t k, int64_t n, int leaf, int tile) {
+  int count = 0;
+  if (semiring != BMM_GF2 && semiring != BMM_BOOLEAN) return fail(BMM_E_INVAL, "bad semiring");
+  BMM_TRY(bmm_leaf_tiles(leaf, &count));
+  if (tile < 1 || tile > count) return fail(BMM_E_INVAL, "bad tile %d", tile);
+  std::lock_guard<std::mutex> lock(g_mu);
+  g_tune[{semiring, m, k, n}] = {leaf, tile};
+  return BMM_OK;
+}
+
+int bmm_autotune_cubic(int semiring, int64_t m, int64_t k, int64_t n, int* leaf_out,
+                       int* tile_out, double* seconds_out) {
+  if (semiring != BMM_GF2 && semiring != BMM_BOOLEAN) return fail(BMM_E_INVAL, "bad semiring");
+  if (m <= 0 || k <= 0 || n <= 0) return fail(BMM_E_INVAL, "sizes must be positive");
+  const int64_t kw = words_of(k), nw = words_of(n);
+  uint64_t *A = nullptr, *BT = nullptr, *C = nullptr;
+  const size_t ba = (size_t)m * kw * 8, bb = (size_t)n * kw * 8, bc = (size_t)m * nw * 8;
+  if (hipMalloc((void**)&A, ba) != hipSuccess || hipMalloc((void**)&BT, bb) != hipSuccess ||
+      hipMalloc((void**)&C, bc) != hipSuccess) {
+    (void)hipGetLastError();
+    hipFree(A);
+    hipFree(BT);
+    hipFree(C);
+    return fail(BMM_E_NOMEM, "autotune buffers");
+  }
+  int rc = BMM_OK;
+  double best = 1e30;
+  int best_leaf = BMM_LEAF_MFMA_I8, best_tile = 1;
+  hipEvent_t e0, e1;
+  hipEventCreate(&e0);
+  hipEventCreate(&e1);
+  hipMemsetD32((hipDeviceptr_t)A, 0x5A5A5A5A, ba / 4);
+  hipMemsetD32((hipDeviceptr_t)BT, 0x3C3C3C3C, bb / 4);
+  std::vector<std::pair<int, int>> cands = {{BMM_LEAF_VALU, 1}};
+  for (int t = 1; t <= MFMA_NUM_TILES; ++t) cands.push_back({BMM_LEAF_MFMA_I8, t});
+  for (auto [leaf, tile] : cands) {
+    LeafBatch p{A, kw, 0, BT, kw, 0, C, nw, 0, m, k, n, 1, 0};
+    rc = run_leaf(semiring, leaf, tile, p, nullptr);  // warm-up
+    if (rc != BMM_OK) break;
+    const int reps = 3;
+    hipEventRecord(e0, nullptr);
+    for (int r = 0; r < reps && rc == BMM_OK; ++r) rc = run_leaf(semiring, leaf, tile, p, nullptr);
+    hipEventRecord(e1, nullptr);
+    if (rc != BMM_OK) break;
+    if (hipEventSynchronize(e1) != hipSuccess) {
+      rc = check_hip(hipGetLastError(), "autotune sync");
+      break;
+    }
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, e0, e1);
+    const double sec = ms * 1e-3 / reps;
+    if (sec < best) {
+      best = sec;
+      best_leaf = leaf;
+      best_tile = tile;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  hipFree(A);
+  hipFree(BT);
+  hipFree(C);
+  if (rc != BMM_OK) return rc;
+  BMM_TRY(bmm_autotune_set(semiring, m, k, n, best_leaf, best_tile));
+  if (leaf_out) *leaf_out = best_leaf;
+  if (tile_out) *tile_out = best_tile;
+  if (seconds_out) *seconds_out = best;
+  return BMM_OK;
+}
+
+int bmm_autotune_save(const char* path) {
+  if (!path) return fail(BMM_E_INVAL, "null path");
+  std::ofstream f(path);
+  if (!f) return fail(BMM_E_INVAL, "cannot write %s", path);
+  std::lock_guard<std::mutex> lock(g_mu);
+  f << "# bmm autotune table: semiring m k n leaf tile\n";
+  for (auto& [key, val] : g_tune)
+    f << key.semiring << ' ' << key.m << ' ' << key.k << ' ' << key.n << ' ' << val.first << ' '
+      << val.second << '\n';
+  return f ? BMM_OK : fail(BMM_E_INVAL, "write failed: %s", path);
+}
+
+int bmm_autotune_load(const char* path) {
+  if (!path) return fail(BMM_E_INVAL, "null path");
+  std::ifstream f(path);
+  if (!f) return fail(BMM_E_INVAL, "cannot read %s", path);
+  std::string line;
+  int loaded = 0;
+  while (std::getline(f, line)) {
+    if (line.empty() || line[0] == '#') continue;
+    int sr, leaf, tile;
+    long long m, k, n;
+    if (sscanf(line.c_str(), "%d %lld %lld %lld %d %d", &sr, &m, &k, &n, &leaf, &tile) != 6)
+      return fail(BMM_E_INVAL, "bad line in %s: %s", path, line.c_str());
+    BMM_TRY(bmm_autotune_set(sr, m, k, n, leaf, tile));
+    ++loaded;
+  }
+  return BMM_OK;
+}
+
+const char* bmm_status_string(int status) {
+  switch (status) {
+    case BMM_OK: return "ok";
+    case BMM_E_INVAL: return "invalid argument";
+    case BMM_E_UNSUPPORTED: return "unsupported";
+    case BMM_E_WORKSPACE: return "workspace too small";
+    case BMM_E_NOMEM: return "out of memory";
+    case BMM_E_DEVICE: return "device error";
+    default: return "unknown status";
+  }
+}
+
+const char* bmm_last_error(void) { return g_last_error.c_str(); }
+
+const char* bmm_version(void) { return "bmm 0.1 (gfx950)"; }
+
+void bmm_finalize(void) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  if (!g_scratch.empty()) (void)hipDeviceSynchronize();
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  for (auto& [dev, slot] : g_scratch) {
+    if (slot.first) {
+      (void)hipSetDevice(dev);
+      (void)hipFree(slot.first);
+    }
+  }
+  (void)hipSetDevice(cur);
+  g_scratch.clear();
+  g_tune.clear();
+}
+
+}  // extern "C"

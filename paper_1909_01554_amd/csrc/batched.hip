@@ -1,0 +1,71 @@
+// Persistent batched leaf: many independent products of uneven sizes in one
+// launch.  Each wave pulls 64 x 64 output tiles from a device-wide counter
+// until the queue is empty; a tile's problem is found by binary search over
+// the per-problem tile prefix sums.  The tile itself is the int8-MFMA leaf
+// (mfma_tile.h).  The plan orders problems by decreasing k (longest tiles
+// first), so the queue drains with a short tail.  A separate one-thread kernel
+// zeroes the counter before each launch, so the pair can be captured into a
+// HIP graph and replayed.
+#include "mfma_tile.h"
+
+namespace bmm {
+namespace {
+
+__global__ void reset_counter(unsigned int* counter) {
+  if (threadIdx.x == 0) *counter = 0u;
+}
+
+template <int KV>
+__device__ __forceinline__ void run_tile(const BatchedDesc& d, int64_t tm, int64_t tn) {
+  if (d.semiring == GF2)
+    mfma::tile<GF2, 2, 2, KV>(d.A, d.lda, d.BT, d.ldbt, d.C, d.ldc, d.m, d.k, d.n, tm, tn, 0);
+  else
+    mfma::tile<BOOLEAN, 2, 2, KV>(d.A, d.lda, d.BT, d.ldbt, d.C, d.ldc, d.m, d.k, d.n, tm, tn,
+                                  0);
+}
+
+__global__ __launch_bounds__(256) void batched_kernel(const BatchedDesc* __restrict__ descs,
+                                                      int64_t count, int64_t total_tiles,
+                                                      unsigned int* __restrict__ counter) {
+  const int lane = threadIdx.x & 63;
+  while (true) {
+    unsigned int t = 0;
+    if (lane == 0) t = atomicAdd(counter, 1u);
+    t = __shfl(t, 0);
+    if ((int64_t)t >= total_tiles) break;  // every wave exits once the queue is drained
+    // binary search: last problem with tile_begin <= t
+    int64_t lo = 0, hi = count - 1;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi + 1) >> 1;
+      if (descs[mid].tile_begin <= (int64_t)t) lo = mid;
+      else hi = mid - 1;
+    }
+    const BatchedDesc d = descs[lo];
+    const int64_t local = (int64_t)t - d.tile_begin;
+    const int64_t tm = local / d.tiles_n;
+    const int64_t tn = local - tm * d.tiles_n;
+    const bool aligned = ((reinterpret_cast<uintptr_t>(d.A) | reinterpret_cast<uintptr_t>(d.BT)) & 15) == 0 &&
+                         ((d.lda | d.ldbt) & 1) == 0;
+    if (aligned) run_tile<2>(d, tm, tn);
+    else run_tile<1>(d, tm, tn);
+  }
+}
+
+}  // namespace
+
+int batched_tile_rows() { return 64; }
+int batched_tile_cols() { return 64; }
+
+hipError_t launch_batched_persistent(const BatchedDesc* descs, int64_t count,
+                                     int64_t total_tiles, unsigned int* counter, int grid,
+                                     hipStream_t s) {
+  if (count <= 0 || total_tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(reset_counter, dim3(1), dim3(64), 0, s, counter);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(batched_kernel, dim3((unsigned)grid), dim3(256), 0, s, descs, count,
+                     total_tiles, counter);
+  return hipGetLastError();
+}
+
+}  // namespace bmm

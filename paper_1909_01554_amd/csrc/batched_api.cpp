@@ -1,0 +1,203 @@
+// Batched products: plan construction (device-resident problem table sorted by
+// decreasing k) and launches of the persistent kernel.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/bmm.h"
+#include "bmm_internal.h"
+
+using namespace bmm;
+
+namespace {
+
+#define bfail bmm::set_error
+
+struct Plan {
+  BatchedDesc* descs = nullptr;  // device
+  unsigned int* counter = nullptr;
+  int64_t count = 0;
+  int64_t total_tiles = 0;
+  int grid = 0;
+  int device = 0;
+};
+
+int validate_problem(const bmm_problem& p, int64_t i) {
+  if (p.semiring != BMM_GF2 && p.semiring != BMM_BOOLEAN)
+    return bfail(BMM_E_INVAL, "problem %ld: bad semiring", (long)i);
+  if (p.m < 0 || p.k < 0 || p.n < 0) return bfail(BMM_E_INVAL, "problem %ld: negative size", (long)i);
+  if (p.m == 0 || p.n == 0) return BMM_OK;
+  const int64_t kw = (p.k + 63) / 64, nw = (p.n + 63) / 64;
+  if (!p.C || p.ldc < nw) return bfail(BMM_E_INVAL, "problem %ld: bad C or ldc", (long)i);
+  if (p.k > 0) {
+    if (!p.A || !p.B) return bfail(BMM_E_INVAL, "problem %ld: null A or B", (long)i);
+    if (p.lda < kw) return bfail(BMM_E_INVAL, "problem %ld: lda too small", (long)i);
+    if (p.b_transposed ? p.ldb < kw : p.ldb < nw)
+      return bfail(BMM_E_INVAL, "problem %ld: ldb too small", (long)i);
+  }
+  if (((uintptr_t)p.A | (uintptr_t)p.B | (uintptr_t)p.C) & 7)
+    return bfail(BMM_E_INVAL, "problem %ld: pointers must be 8-byte aligned", (long)i);
+  return BMM_OK;
+}
+
+int build_plan(const bmm_problem* problems, int64_t count, Plan* out) {
+  if (count < 0 || (count > 0 && !problems)) return bfail(BMM_E_INVAL, "bad problem list");
+  std::vector<int64_t> order;
+  for (int64_t i = 0; i < count; ++i) {
+    int rc = validate_problem(problems[i], i);
+    if (rc != BMM_OK) return rc;
+    if (!problems[i].b_transposed)
+      return bfail(BMM_E_INVAL, "problem %ld: plans need B passed transposed", (long)i);
+    if (problems[i].m > 0 && problems[i].n > 0) order.push_back(i);
+  }
+  std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+    return problems[a].k > problems[b].k;
+  });
+  const int TR = batched_tile_rows(), TC = batched_tile_cols();
+  std::vector<BatchedDesc> host;
+  int64_t tiles = 0;
+  for (int64_t i : order) {
+    const bmm_problem& p = problems[i];
+    BatchedDesc d;
+    d.A = p.A;
+    d.BT = p.B;
+    d.C = p.C;
+    d.lda = p.lda;
+    d.ldbt = p.ldb;
+    d.ldc = p.ldc;
+    d.m = p.m;
+    d.k = p.k;
+    d.n = p.n;
+    d.tile_begin = tiles;
+    d.semiring = p.semiring;
+    d.tiles_n = (int32_t)((p.n + TC - 1) / TC);
+    tiles += ((p.m + TR - 1) / TR) * d.tiles_n;
+    host.push_back(d);
+  }
+  Plan P;
+  P.count = (int64_t)host.size();
+  P.total_tiles = tiles;
+  if (hipGetDevice(&P.device) != hipSuccess) return bfail(BMM_E_DEVICE, "hipGetDevice");
+  int cus = 256;
+  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, P.device);
+  P.grid = std::max(1, cus * 4);
+  if (P.count > 0) {
+    if (hipMalloc((void**)&P.descs, sizeof(BatchedDesc) * host.size()) != hipSuccess ||
+        hipMalloc((void**)&P.counter, 256) != hipSuccess) {
+      (void)hipGetLastError();
+      hipFree(P.descs);
+      return bfail(BMM_E_NOMEM, "plan allocation");
+    }
+    if (hipMemcpy(P.descs, host.data(), sizeof(BatchedDesc) * host.size(),
+                  hipMemcpyHostToDevice) != hipSuccess) {
+      hipFree(P.descs);
+      hipFree(P.counter);
+      return bfail(BMM_E_DEVICE, "plan upload: %s", hipGetErrorString(hipGetLastError()));
+    }
+  }
+  *out = P;
+  return BMM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int bmm_batched_plan_create(const bmm_problem* problems, int64_t count,
+                            const bmm_options* /*opt*/, void** plan_out) {
+  if (!plan_out) return bfail(BMM_E_INVAL, "null plan_out");
+  Plan* P = new Plan();
+  int rc = build_plan(problems, count, P);
+  if (rc != BMM_OK) {
+    delete P;
+    return rc;
+  }
+  *plan_out = P;
+  return BMM_OK;
+}
+
+int bmm_batched_plan_launch(void* plan, void* hip_stream) {
+  if (!plan) return bfail(BMM_E_INVAL, "null plan");
+  Plan* P = static_cast<Plan*>(plan);
+  hipError_t e = launch_batched_persistent(P->descs, P->count, P->total_tiles, P->counter,
+                                           P->grid, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return bfail(BMM_E_DEVICE, "batched launch: %s", hipGetErrorString(e));
+  return BMM_OK;
+}
+
+void bmm_batched_plan_destroy(void* plan) {
+  if (!plan) return;
+  Plan* P = static_cast<Plan*>(plan);
+  if (P->descs || P->counter) {
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(P->device);
+    (void)hipDeviceSynchronize();
+    (void)hipFree(P->descs);
+    (void)hipFree(P->counter);
+    (void)hipSetDevice(cur);
+  }
+  delete P;
+}
+
+int bmm_batched(const bmm_problem* problems, int64_t count, const bmm_options* opt,
+                void* hip_stream) {
+  if (count < 0 || (count > 0 && !problems)) return bfail(BMM_E_INVAL, "bad problem list");
+  if (count == 0) return BMM_OK;
+  hipStream_t s = (hipStream_t)hip_stream;
+  // Stage non-transposed right operands into one scratch allocation.
+  std::vector<bmm_problem> probs(problems, problems + count);
+  size_t need = 0;
+  for (int64_t i = 0; i < count; ++i) {
+    int rc = validate_problem(probs[i], i);
+    if (rc != BMM_OK) return rc;
+    if (!probs[i].b_transposed && probs[i].m > 0 && probs[i].n > 0 && probs[i].k > 0)
+      need += (size_t)probs[i].n * ((probs[i].k + 63) / 64) * 8;
+  }
+  uint64_t* stage = nullptr;
+  if (need) {
+    if (hipMalloc((void**)&stage, need) != hipSuccess) {
+      (void)hipGetLastError();
+      return bfail(BMM_E_NOMEM, "batched staging of %zu bytes", need);
+    }
+    size_t off = 0;
+    for (int64_t i = 0; i < count; ++i) {
+      bmm_problem& p = probs[i];
+      if (p.b_transposed || p.m == 0 || p.n == 0 || p.k == 0) {
+        p.b_transposed = 1;
+        if (p.k == 0) p.ldb = std::max<int64_t>(p.ldb, 0);
+        continue;
+      }
+      const int64_t kw = (p.k + 63) / 64;
+      uint64_t* bt = stage + off / 8;
+      hipError_t e = launch_transpose(p.B, p.ldb, 0, bt, kw, 0, p.k, p.n, 1, s);
+      if (e != hipSuccess) {
+        hipFree(stage);
+        return bfail(BMM_E_DEVICE, "transpose: %s", hipGetErrorString(e));
+      }
+      p.B = bt;
+      p.ldb = kw;
+      p.b_transposed = 1;
+      off += (size_t)p.n * kw * 8;
+    }
+  } else {
+    for (auto& p : probs) p.b_transposed = 1;
+  }
+  void* plan = nullptr;
+  int rc = bmm_batched_plan_create(probs.data(), count, opt, &plan);
+  if (rc == BMM_OK) rc = bmm_batched_plan_launch(plan, hip_stream);
+  if (rc == BMM_OK && hipStreamSynchronize(s) != hipSuccess)
+    rc = bfail(BMM_E_DEVICE, "batched sync: %s", hipGetErrorString(hipGetLastError()));
+  bmm_batched_plan_destroy(plan);
+  if (stage) {
+    (void)hipStreamSynchronize(s);
+    hipFree(stage);
+  }
+  return rc;
+}
+
+}  // extern "C"

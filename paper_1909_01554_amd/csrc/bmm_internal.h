@@ -1,0 +1,95 @@
+// Internal interface between the C-ABI layer (api.cpp) and the HIP kernels.
+//
+// Layout everywhere: packed row-major uint64, bit j of a row at bit j % 64 of
+// word j / 64.  "BT" operands are the right-hand operand stored transposed
+// (one row per column of B, k bits long), which is what both leaf kernels read.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bmm {
+
+enum Semiring { GF2 = 0, BOOLEAN = 1 };
+
+// Record a message for bmm_last_error() (thread-local) and return `code`.
+int set_error(int code, const char* fmt, ...);
+
+// A batch of independent leaf products C_b (m x n) = A_b (m x k) * B_b (k x n),
+// with B_b given transposed as BT_b (n x k).  Operand b starts at base + b*stride
+// (strides in words).  accumulate: C ^= AB (GF(2)) or C |= AB (Boolean).
+struct LeafBatch {
+  const uint64_t* A;
+  int64_t lda, strideA;
+  const uint64_t* BT;
+  int64_t ldbt, strideB;
+  uint64_t* C;
+  int64_t ldc, strideC;
+  int64_t m, k, n, batch;
+  int accumulate;
+};
+
+// MFMA leaf variants (rows x cols of C per wave).
+enum MfmaTile { MFMA_128x64 = 0, MFMA_64x64 = 1, MFMA_64x128 = 2, MFMA_64x32 = 3,
+                MFMA_NUM_TILES };
+
+hipError_t launch_leaf_mfma(int semiring, const LeafBatch& p, int tile, hipStream_t s);
+hipError_t launch_leaf_valu(int semiring, const LeafBatch& p, int tile, hipStream_t s);
+int leaf_mfma_tile_rows(int tile);
+int leaf_mfma_tile_cols(int tile);
+
+// dst (cols x rows bits) = transpose of src (rows x cols bits), batched.
+hipError_t launch_transpose(const uint64_t* src, int64_t lds, int64_t strideS,
+                            uint64_t* dst, int64_t ldd, int64_t strideD,
+                            int64_t rows, int64_t cols, int64_t batch, hipStream_t s);
+
+// 2x2 basis change of the self-inverse design applied at the top `depth`
+// levels of every matrix of a batch (rows and row words divisible by 2^depth),
+// in place.  inverse = 0: phi (forward, both operands), 1: chi (result).
+hipError_t launch_basis(uint64_t* X, int64_t ld, int64_t stride, int64_t rows,
+                        int64_t row_words, int64_t batch, int depth, int inverse,
+                        hipStream_t s);
+
+// One recursion level.  Parent p of a batch (rows x words, pitch ldp, stride
+// strideP) expands into 7 children stored contiguously: child (p, h) is
+// matrix 7p + h of `dst`, each (rows/2) x (words/2) with pitch words/2.
+// side 0: left operand (alpha), 1: right operand stored transposed (beta with
+// the 01 and 10 quadrants swapped).
+hipError_t launch_expand(int side, const uint64_t* src, int64_t ldp, int64_t strideP,
+                         uint64_t* dst, int64_t rows, int64_t words, int64_t parents,
+                         hipStream_t s);
+// Two recursion levels at once (49 grandchildren per parent, index 49p + 7h1 + h2).
+hipError_t launch_expand2(int side, const uint64_t* src, int64_t ldp, int64_t strideP,
+                          uint64_t* dst, int64_t rows, int64_t words, int64_t parents,
+                          hipStream_t s);
+// Inverse of the above for the products: 7 children (compact, (rows/2) x
+// (words/2)) of parent p combine by gamma into the parent's 4 quadrants.
+hipError_t launch_compress(const uint64_t* src, uint64_t* dst, int64_t ldp, int64_t strideP,
+                           int64_t rows, int64_t words, int64_t parents, hipStream_t s);
+hipError_t launch_compress2(const uint64_t* src, uint64_t* dst, int64_t ldp,
+                            int64_t strideP, int64_t rows, int64_t words, int64_t parents,
+                            hipStream_t s);
+
+// Copy a batch of rows x words matrices (used to stage operands).
+hipError_t launch_copy(const uint64_t* src, int64_t lds, uint64_t* dst, int64_t ldd,
+                       int64_t rows, int64_t words, hipStream_t s);
+// Zero a rows x words matrix (a fill kernel, safe under graph capture).
+hipError_t launch_zero(uint64_t* dst, int64_t ld, int64_t rows, int64_t words, hipStream_t s);
+
+// Persistent batched leaf over a device-resident problem table.
+struct BatchedDesc {
+  const uint64_t* A;
+  const uint64_t* BT;
+  uint64_t* C;
+  int64_t lda, ldbt, ldc;
+  int64_t m, k, n;
+  int64_t tile_begin;  // prefix sum of tiles over problems
+  int32_t semiring, tiles_n;
+};
+hipError_t launch_batched_persistent(const BatchedDesc* descs, int64_t count,
+                                     int64_t total_tiles, unsigned int* counter,
+                                     int grid, hipStream_t s);
+int batched_tile_rows();
+int batched_tile_cols();
+
+}  // namespace bmm

@@ -1,0 +1,299 @@
+// Expanding and compressing levels of the alternative-basis recursion
+// (sections 3.8, 3.9, 3.11; Algorithms 1 and 2 of the paper) for the
+// self-inverse design (eqs. mb-tsrecurrence and mb-qrecurrence, matrix form
+// eq. mb-albega).
+//
+// Expansion (left operand, alpha):
+//   T0 = A00, T1 = A01, T2 = A10, T3 = A11,
+//   T4 = A00 + A11, T5 = A01 + A11, T6 = A10 + A11
+// Expansion (right operand, beta):
+//   S0 = B00, S1 = B10, S2 = B00 + B11, S3 = B11,
+//   S4 = B01, S5 = B01 + B11, S6 = B10 + B11
+// The right operand is kept transposed throughout (its quadrant (j, k) lives
+// at (k, j)), so the right expansion reads the stored 01 quadrant as B10 and
+// the stored 10 quadrant as B01; each S_h is then produced already transposed.
+// Compression (gamma):
+//   C00 = Q0 + Q1, C01 = Q4 + Q6, C10 = Q2 + Q5, C11 = Q1 + Q3 + Q5 + Q6
+//
+// Every thread owns one 64-bit word position of a child (or grandchild) and
+// moves it through registers: one level reads 4 words and writes 7 (expand)
+// or reads 7 and writes 4 (compress); the merged two-level kernels read 16 and
+// write 49, or read 49 and write 16, so the intermediate level never goes to
+// HBM (section 3.15, merging levels).  Children of parent p are matrices
+// 7p + h, grandchildren 49p + 7h1 + h2, stored compactly one after another.
+#include "bmm_internal.h"
+
+namespace bmm {
+namespace {
+
+template <int SIDE>
+__device__ __forceinline__ void expand_one(uint64_t q00, uint64_t q01, uint64_t q10,
+                                           uint64_t q11, uint64_t (&o)[7]) {
+  if (SIDE == 0) {
+    o[0] = q00;
+    o[1] = q01;
+    o[2] = q10;
+    o[3] = q11;
+    o[4] = q00 ^ q11;
+    o[5] = q01 ^ q11;
+    o[6] = q10 ^ q11;
+  } else {
+    // stored transposed: B01 is the stored 10 quadrant, B10 the stored 01 quadrant
+    const uint64_t b00 = q00, b01 = q10, b10 = q01, b11 = q11;
+    o[0] = b00;
+    o[1] = b10;
+    o[2] = b00 ^ b11;
+    o[3] = b11;
+    o[4] = b01;
+    o[5] = b01 ^ b11;
+    o[6] = b10 ^ b11;
+  }
+}
+
+__device__ __forceinline__ void compress_one(const uint64_t (&q)[7], uint64_t& c00,
+                                             uint64_t& c01, uint64_t& c10, uint64_t& c11) {
+  c00 = q[0] ^ q[1];
+  c01 = q[4] ^ q[6];
+  c10 = q[2] ^ q[5];
+  c11 = q[1] ^ q[3] ^ q[5] ^ q[6];
+}
+
+template <int SIDE>
+__global__ __launch_bounds__(256) void expand_kernel(const uint64_t* __restrict__ src,
+                                                     int64_t ldp, int64_t strideP,
+                                                     uint64_t* __restrict__ dst, int64_t rows,
+                                                     int64_t words, int64_t parents) {
+  const int64_t hr = rows >> 1, hw = words >> 1;
+  const int64_t csize = hr * hw;
+  const int64_t total = csize * parents;
+  const int64_t gstride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gstride) {
+    const int64_t p = e / csize;
+    const int64_t q = e - p * csize;
+    const int64_t r = q / hw;
+    const int64_t w = q - r * hw;
+    const uint64_t* P = src + p * strideP;
+    const uint64_t q00 = P[r * ldp + w];
+    const uint64_t q01 = P[r * ldp + hw + w];
+    const uint64_t q10 = P[(r + hr) * ldp + w];
+    const uint64_t q11 = P[(r + hr) * ldp + hw + w];
+    uint64_t o[7];
+    expand_one<SIDE>(q00, q01, q10, q11, o);
+    uint64_t* D = dst + 7 * p * csize + q;
+#pragma unroll
+    for (int h = 0; h < 7; ++h) D[h * csize] = o[h];
+  }
+}
+
+template <int SIDE>
+__global__ __launch_bounds__(256) void expand2_kernel(const uint64_t* __restrict__ src,
+                                                      int64_t ldp, int64_t strideP,
+                                                      uint64_t* __restrict__ dst, int64_t rows,
+                                                      int64_t words, int64_t parents) {
+  const int64_t qr = rows >> 2, qw = words >> 2;
+  const int64_t gsize = qr * qw;
+  const int64_t total = gsize * parents;
+  const int64_t gstride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gstride) {
+    const int64_t p = e / gsize;
+    const int64_t q = e - p * gsize;
+    const int64_t r = q / qw;
+    const int64_t w = q - r * qw;
+    const uint64_t* P = src + p * strideP + r * ldp + w;
+    // x[i1][j1][i2][j2] at row i1*2qr + i2*qr + r, word j1*2qw + j2*qw + w
+    uint64_t x[2][2][2][2];
+#pragma unroll
+    for (int i1 = 0; i1 < 2; ++i1)
+#pragma unroll
+      for (int j1 = 0; j1 < 2; ++j1)
+#pragma unroll
+        for (int i2 = 0; i2 < 2; ++i2)
+#pragma unroll
+          for (int j2 = 0; j2 < 2; ++j2)
+            x[i1][j1][i2][j2] = P[(i1 * 2 * qr + i2 * qr) * ldp + j1 * 2 * qw + j2 * qw];
+    // first level: for each inner quadrant (i2, j2), expand over (i1, j1)
+    uint64_t t[7][2][2];
+#pragma unroll
+    for (int i2 = 0; i2 < 2; ++i2)
+#pragma unroll
+      for (int j2 = 0; j2 < 2; ++j2) {
+        uint64_t o[7];
+        expand_one<SIDE>(x[0][0][i2][j2], x[0][1][i2][j2], x[1][0][i2][j2], x[1][1][i2][j2], o);
+#pragma unroll
+        for (int h = 0; h < 7; ++h) t[h][i2][j2] = o[h];
+      }
+    uint64_t* D = dst + 49 * p * gsize + q;
+#pragma unroll
+    for (int h1 = 0; h1 < 7; ++h1) {
+      uint64_t o[7];
+      expand_one<SIDE>(t[h1][0][0], t[h1][0][1], t[h1][1][0], t[h1][1][1], o);
+#pragma unroll
+      for (int h2 = 0; h2 < 7; ++h2) D[(7 * h1 + h2) * gsize] = o[h2];
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void compress_kernel(const uint64_t* __restrict__ src,
+                                                       uint64_t* __restrict__ dst, int64_t ldp,
+                                                       int64_t strideP, int64_t rows,
+                                                       int64_t words, int64_t parents) {
+  const int64_t hr = rows >> 1, hw = words >> 1;
+  const int64_t csize = hr * hw;
+  const int64_t total = csize * parents;
+  const int64_t gstride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gstride) {
+    const int64_t p = e / csize;
+    const int64_t q = e - p * csize;
+    const int64_t r = q / hw;
+    const int64_t w = q - r * hw;
+    const uint64_t* S = src + 7 * p * csize + q;
+    uint64_t v[7];
+#pragma unroll
+    for (int h = 0; h < 7; ++h) v[h] = S[h * csize];
+    uint64_t c00, c01, c10, c11;
+    compress_one(v, c00, c01, c10, c11);
+    uint64_t* P = dst + p * strideP;
+    P[r * ldp + w] = c00;
+    P[r * ldp + hw + w] = c01;
+    P[(r + hr) * ldp + w] = c10;
+    P[(r + hr) * ldp + hw + w] = c11;
+  }
+}
+
+__global__ __launch_bounds__(256) void compress2_kernel(const uint64_t* __restrict__ src,
+                                                        uint64_t* __restrict__ dst, int64_t ldp,
+                                                        int64_t strideP, int64_t rows,
+                                                        int64_t words, int64_t parents) {
+  const int64_t qr = rows >> 2, qw = words >> 2;
+  const int64_t gsize = qr * qw;
+  const int64_t total = gsize * parents;
+  const int64_t gstride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gstride) {
+    const int64_t p = e / gsize;
+    const int64_t q = e - p * gsize;
+    const int64_t r = q / qw;
+    const int64_t w = q - r * qw;
+    const uint64_t* S = src + 49 * p * gsize + q;
+    // inner level: for each h1, combine the seven h2 products into quadrants (i2, k2)
+    uint64_t c[7][2][2];
+#pragma unroll
+    for (int h1 = 0; h1 < 7; ++h1) {
+      uint64_t v[7];
+#pragma unroll
+      for (int h2 = 0; h2 < 7; ++h2) v[h2] = S[(7 * h1 + h2) * gsize];
+      compress_one(v, c[h1][0][0], c[h1][0][1], c[h1][1][0], c[h1][1][1]);
+    }
+    uint64_t* P = dst + p * strideP + r * ldp + w;
+#pragma unroll
+    for (int i2 = 0; i2 < 2; ++i2)
+#pragma unroll
+      for (int k2 = 0; k2 < 2; ++k2) {
+        uint64_t v[7];
+#pragma unroll
+        for (int h1 = 0; h1 < 7; ++h1) v[h1] = c[h1][i2][k2];
+        uint64_t c00, c01, c10, c11;
+        compress_one(v, c00, c01, c10, c11);
+        const int64_t off = i2 * qr * ldp + k2 * qw;
+        P[off] = c00;
+        P[off + 2 * qw] = c01;
+        P[off + 2 * qr * ldp] = c10;
+        P[off + 2 * qr * ldp + 2 * qw] = c11;
+      }
+  }
+}
+
+__global__ __launch_bounds__(256) void copy_kernel(const uint64_t* __restrict__ src, int64_t lds,
+                                                   uint64_t* __restrict__ dst, int64_t ldd,
+                                                   int64_t rows, int64_t words) {
+  const int64_t total = rows * words;
+  const int64_t gstride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gstride) {
+    const int64_t r = e / words;
+    const int64_t w = e - r * words;
+    dst[r * ldd + w] = src[r * lds + w];
+  }
+}
+
+__global__ __launch_bounds__(256) void zero_kernel(uint64_t* __restrict__ dst, int64_t ld,
+                                                   int64_t rows, int64_t words) {
+  const int64_t total = rows * words;
+  const int64_t gstride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gstride) {
+    const int64_t r = e / words;
+    const int64_t w = e - r * words;
+    dst[r * ld + w] = 0ull;
+  }
+}
+
+inline unsigned grid_for(int64_t total) {
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > 32768) blocks = 32768;
+  if (blocks < 1) blocks = 1;
+  return (unsigned)blocks;
+}
+
+}  // namespace
+
+hipError_t launch_expand(int side, const uint64_t* src, int64_t ldp, int64_t strideP,
+                         uint64_t* dst, int64_t rows, int64_t words, int64_t parents,
+                         hipStream_t s) {
+  const int64_t total = (rows >> 1) * (words >> 1) * parents;
+  if (total <= 0) return hipSuccess;
+  if (side == 0)
+    hipLaunchKernelGGL(expand_kernel<0>, dim3(grid_for(total)), dim3(256), 0, s, src, ldp,
+                       strideP, dst, rows, words, parents);
+  else
+    hipLaunchKernelGGL(expand_kernel<1>, dim3(grid_for(total)), dim3(256), 0, s, src, ldp,
+                       strideP, dst, rows, words, parents);
+  return hipGetLastError();
+}
+
+hipError_t launch_expand2(int side, const uint64_t* src, int64_t ldp, int64_t strideP,
+                          uint64_t* dst, int64_t rows, int64_t words, int64_t parents,
+                          hipStream_t s) {
+  const int64_t total = (rows >> 2) * (words >> 2) * parents;
+  if (total <= 0) return hipSuccess;
+  if (side == 0)
+    hipLaunchKernelGGL(expand2_kernel<0>, dim3(grid_for(total)), dim3(256), 0, s, src, ldp,
+                       strideP, dst, rows, words, parents);
+  else
+    hipLaunchKernelGGL(expand2_kernel<1>, dim3(grid_for(total)), dim3(256), 0, s, src, ldp,
+                       strideP, dst, rows, words, parents);
+  return hipGetLastError();
+}
+
+hipError_t launch_compress(const uint64_t* src, uint64_t* dst, int64_t ldp, int64_t strideP,
+                           int64_t rows, int64_t words, int64_t parents, hipStream_t s) {
+  const int64_t total = (rows >> 1) * (words >> 1) * parents;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(compress_kernel, dim3(grid_for(total)), dim3(256), 0, s, src, dst, ldp,
+                     strideP, rows, words, parents);
+  return hipGetLastError();
+}
+
+hipError_t launch_compress2(const uint64_t* src, uint64_t* dst, int64_t ldp, int64_t strideP,
+                            int64_t rows, int64_t words, int64_t parents, hipStream_t s) {
+  const int64_t total = (rows >> 2) * (words >> 2) * parents;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(compress2_kernel, dim3(grid_for(total)), dim3(256), 0, s, src, dst, ldp,
+                     strideP, rows, words, parents);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(const uint64_t* src, int64_t lds, uint64_t* dst, int64_t ldd,
+                       int64_t rows, int64_t words, hipStream_t s) {
+  const int64_t total = rows * words;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(copy_kernel, dim3(grid_for(total)), dim3(256), 0, s, src, lds, dst, ldd,
+                     rows, words);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(uint64_t* dst, int64_t ld, int64_t rows, int64_t words, hipStream_t s) {
+  const int64_t total = rows * words;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(zero_kernel, dim3(grid_for(total)), dim3(256), 0, s, dst, ld, rows, words);
+  return hipGetLastError();
+}
+
+}  // namespace bmm

@@ -1,0 +1,100 @@
+// Cubic leaf product on the int8 matrix cores of gfx950.
+//
+// The cubic product C[i][k] = SUM_j A[i][j] B[j][k] (GF(2): XOR, Boolean: OR)
+// is an integer dot product reduced at the end: the int32 count of j with
+// A[i][j] = B[j][k] = 1 gives the GF(2) bit as its parity and the Boolean bit
+// as (count > 0).  Counts stay exact because k < 2^31.
+//
+// Each wave owns a TM x TN tile of C (TM = 32*RA, TN = 32*RB) and issues
+// v_mfma_i32_32x32x32_i8 on RA x RB accumulator blocks held in registers.
+// Operands never touch HBM as bytes: every lane reads 64-bit words of packed
+// bits straight from its row of A (or of B transposed) and expands them in
+// registers.  The order of k inside a dot product is free as long as A and B
+// use the same one, so a 32-bit half x of a word yields the eight dwords
+// x >> d (d = 0..7): byte e of dword d carries bit 8e + d of x in its lowest
+// bit.  For GF(2) only that lowest bit matters (a product of two bytes is odd
+// iff both low bits are 1), so one shift makes four operand bytes; the Boolean
+// count needs exact 0/1 bytes and adds a mask with 0x01010101.
+//
+// The result bits go back to packed rows with wave ballots: accumulator
+// register v of a 32x32 block holds row 8*(v/4) + (v%4) in lanes 0..31 and
+// row 8*(v/4) + 4 + (v%4) in lanes 32..63, one column per lane, so one ballot
+// yields two 32-bit row words.
+#include "mfma_tile.h"
+
+namespace bmm {
+namespace {
+
+constexpr int kWaves = 4;
+
+template <int SEMI, int RA, int RB, int KV>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void leaf_mfma_kernel(LeafBatch p, int64_t tiles_m,
+                                                        int64_t tiles_n) {
+  const int64_t tile = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
+  const int64_t per = tiles_m * tiles_n;
+  const int64_t b = tile / per;
+  if (b >= p.batch) return;  // uniform per wave; no block-level barriers below
+  const int64_t t = tile - b * per;
+  const int64_t tm = t / tiles_n;
+  const int64_t tn = t - tm * tiles_n;
+  mfma::tile<SEMI, RA, RB, KV>(p.A + b * p.strideA, p.lda, p.BT + b * p.strideB, p.ldbt,
+                               p.C + b * p.strideC, p.ldc, p.m, p.k, p.n, tm, tn,
+                               p.accumulate);
+}
+
+template <int SEMI, int RA, int RB>
+hipError_t launch_t(const LeafBatch& p, hipStream_t s) {
+  constexpr int TM = 32 * RA, TN = 32 * RB;
+  const int64_t tiles_m = (p.m + TM - 1) / TM;
+  // cover whole 64-bit output words, so padding dwords are written (as zero)
+  const int64_t tiles_n = (((p.n + 63) / 64) * 64 + TN - 1) / TN;
+  const int64_t total = tiles_m * tiles_n * p.batch;
+  if (total == 0) return hipSuccess;
+  const int64_t blocks = (total + kWaves - 1) / kWaves;
+  const bool aligned16 = ((reinterpret_cast<uintptr_t>(p.A) | reinterpret_cast<uintptr_t>(p.BT)) & 15) == 0 &&
+                         ((p.lda | p.ldbt | p.strideA | p.strideB) & 1) == 0;
+  if (aligned16)
+    hipLaunchKernelGGL((leaf_mfma_kernel<SEMI, RA, RB, 2>), dim3((unsigned)blocks), dim3(256), 0, s,
+                       p, tiles_m, tiles_n);
+  else
+    hipLaunchKernelGGL((leaf_mfma_kernel<SEMI, RA, RB, 1>), dim3((unsigned)blocks), dim3(256), 0, s,
+                       p, tiles_m, tiles_n);
+  return hipGetLastError();
+}
+
+template <int SEMI>
+hipError_t launch_semi(const LeafBatch& p, int tile, hipStream_t s) {
+  switch (tile) {
+    case MFMA_64x64: return launch_t<SEMI, 2, 2>(p, s);
+    case MFMA_64x128: return launch_t<SEMI, 2, 4>(p, s);
+    case MFMA_64x32: return launch_t<SEMI, 2, 1>(p, s);
+    default: return launch_t<SEMI, 4, 2>(p, s);
+  }
+}
+
+}  // namespace
+
+int leaf_mfma_tile_rows(int tile) {
+  switch (tile) {
+    case MFMA_64x64: return 64;
+    case MFMA_64x128: return 64;
+    case MFMA_64x32: return 64;
+    default: return 128;
+  }
+}
+
+int leaf_mfma_tile_cols(int tile) {
+  switch (tile) {
+    case MFMA_64x64: return 64;
+    case MFMA_64x128: return 128;
+    case MFMA_64x32: return 32;
+    default: return 64;
+  }
+}
+
+hipError_t launch_leaf_mfma(int semiring, const LeafBatch& p, int tile, hipStream_t s) {
+  if (p.m <= 0 || p.n <= 0 || p.batch <= 0) return hipSuccess;
+  return semiring == GF2 ? launch_semi<GF2>(p, tile, s) : launch_semi<BOOLEAN>(p, tile, s);
+}
+
+}  // namespace bmm

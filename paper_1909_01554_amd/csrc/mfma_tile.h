@@ -1,0 +1,160 @@
+// Device code of one int8-MFMA leaf tile, shared by the per-launch leaf kernel
+// and the persistent batched kernel.  See leaf_mfma.hip for the method.
+#pragma once
+
+#include "bmm_internal.h"
+
+namespace bmm {
+namespace mfma {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+template <int SEMI>
+__device__ __forceinline__ v4i expand4(uint32_t x, int first) {
+  v4i o;
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    uint32_t e = x >> (first + d);
+    if (SEMI == BOOLEAN) e &= 0x01010101u;
+    o[d] = (int)e;
+  }
+  return o;
+}
+
+template <int SEMI, int RA, int RB>
+__device__ __forceinline__ void mfma_word(const uint64_t (&xa)[RA], const uint64_t (&xb)[RB],
+                                          v16i (&acc)[RA][RB]) {
+#pragma unroll
+  for (int hw = 0; hw < 2; ++hw) {
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      v4i oa[RA], ob[RB];
+#pragma unroll
+      for (int f = 0; f < RA; ++f) oa[f] = expand4<SEMI>((uint32_t)(xa[f] >> (32 * hw)), 4 * s);
+#pragma unroll
+      for (int g = 0; g < RB; ++g) ob[g] = expand4<SEMI>((uint32_t)(xb[g] >> (32 * hw)), 4 * s);
+#pragma unroll
+      for (int f = 0; f < RA; ++f)
+#pragma unroll
+        for (int g = 0; g < RB; ++g)
+          acc[f][g] = __builtin_amdgcn_mfma_i32_32x32x32_i8(oa[f], ob[g], acc[f][g], 0, 0, 0);
+    }
+  }
+}
+
+// KV = 64-bit words per lane per load (1: 8-byte loads, 2: 16-byte loads when
+// the operands are 16-byte aligned).  Lane half h takes words 2*KV*step + KV*h + v.
+template <int SEMI, int RA, int RB, int KV>
+__device__ __forceinline__ void tile(const uint64_t* __restrict__ A, int64_t lda,
+                                     const uint64_t* __restrict__ BT, int64_t ldbt,
+                                     uint64_t* __restrict__ Cm, int64_t ldc, int64_t m,
+                                     int64_t k, int64_t n, int64_t tm, int64_t tn,
+                                     int accumulate) {
+  constexpr int TM = 32 * RA, TN = 32 * RB;
+  const int lane = threadIdx.x & 63;
+  const int half = lane >> 5;
+  const int li = lane & 31;
+  const int64_t kw = (k + 63) >> 6;
+
+  const uint64_t* arow[RA];
+  const uint64_t* brow[RB];
+#pragma unroll
+  for (int f = 0; f < RA; ++f) {
+    int64_t r = tm * TM + 32 * f + li;
+    r = r < m ? r : m - 1;
+    arow[f] = A + r * lda + KV * half;
+  }
+#pragma unroll
+  for (int g = 0; g < RB; ++g) {
+    int64_t c = tn * TN + 32 * g + li;
+    c = c < n ? c : n - 1;
+    brow[g] = BT + c * ldbt + KV * half;
+  }
+
+  v16i acc[RA][RB];
+#pragma unroll
+  for (int f = 0; f < RA; ++f)
+#pragma unroll
+    for (int g = 0; g < RB; ++g) acc[f][g] = v16i{};
+
+  const int64_t full_steps = kw / (2 * KV);
+  for (int64_t st = 0; st < full_steps; ++st) {
+    const int64_t w = st * 2 * KV;
+    uint64_t xa[KV][RA], xb[KV][RB];
+    if constexpr (KV == 2) {
+#pragma unroll
+      for (int f = 0; f < RA; ++f) {
+        const ulonglong2 v = *reinterpret_cast<const ulonglong2*>(arow[f] + w);
+        xa[0][f] = v.x;
+        xa[1][f] = v.y;
+      }
+#pragma unroll
+      for (int g = 0; g < RB; ++g) {
+        const ulonglong2 v = *reinterpret_cast<const ulonglong2*>(brow[g] + w);
+        xb[0][g] = v.x;
+        xb[1][g] = v.y;
+      }
+    } else {
+#pragma unroll
+      for (int f = 0; f < RA; ++f) xa[0][f] = arow[f][w];
+#pragma unroll
+      for (int g = 0; g < RB; ++g) xb[0][g] = brow[g][w];
+    }
+#pragma unroll
+    for (int v = 0; v < KV; ++v) mfma_word<SEMI, RA, RB>(xa[v], xb[v], acc);
+  }
+  // Tail: words past the end of the row read as zero.
+  {
+    const int64_t w = full_steps * 2 * KV;
+    if (w < kw) {
+#pragma unroll
+      for (int v = 0; v < KV; ++v) {
+        const int64_t wi = w + KV * half + v;
+        uint64_t xa[RA], xb[RB];
+#pragma unroll
+        for (int f = 0; f < RA; ++f) xa[f] = wi < kw ? arow[f][w + v] : 0ull;
+#pragma unroll
+        for (int g = 0; g < RB; ++g) xb[g] = wi < kw ? brow[g][w + v] : 0ull;
+        mfma_word<SEMI, RA, RB>(xa, xb, acc);
+      }
+    }
+  }
+
+  // Epilogue: reduce counts to bits and pack 32 columns per dword with ballots.
+  uint32_t* C32 = reinterpret_cast<uint32_t*>(Cm);
+  const int64_t ldc32 = 2 * ldc;
+  const int64_t n_words32 = ((n + 63) >> 6) * 2;  // dwords per C row incl. padding
+  const int myv = ((li >> 3) << 2) | (li & 3);
+  const int myhi = (li >> 2) & 1;
+#pragma unroll
+  for (int g = 0; g < RB; ++g) {
+    const int64_t c0 = tn * TN + 32 * g;
+    const int64_t cw = c0 >> 5;
+    if (cw >= n_words32) continue;  // uniform
+    const int64_t valid = n - c0;
+    const uint32_t cmask = valid >= 32 ? 0xFFFFFFFFu : (valid > 0 ? ((1u << valid) - 1u) : 0u);
+#pragma unroll
+    for (int f = 0; f < RA; ++f) {
+      uint32_t mine = 0;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int cnt = acc[f][g][v];
+        const bool bit = (SEMI == GF2) ? ((cnt & 1) != 0) : (cnt != 0);
+        const uint64_t bal = __ballot(bit);
+        const uint32_t word = myhi ? (uint32_t)(bal >> 32) : (uint32_t)bal;
+        mine = (myv == v) ? word : mine;
+      }
+      mine &= cmask;
+      const int64_t row = tm * TM + 32 * f + li;
+      if (half == 0 && row < m) {
+        uint32_t* dst = C32 + row * ldc32 + cw;
+        if (accumulate) mine = (SEMI == GF2) ? (mine ^ *dst) : (mine | *dst);
+        *dst = mine;
+      }
+    }
+  }
+}
+
+}  // namespace mfma
+}  // namespace bmm

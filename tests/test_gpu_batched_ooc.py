@@ -1,0 +1,106 @@
+"""GPU parity of the persistent batched launch (also replayed from a HIP graph)
+and of the out-of-core pipeline, against the oracle's plain product."""
+import numpy as np
+import pytest
+
+import bmmgen
+import oracle
+from gpu_util import announce, empty_dev, from_dev, to_dev, words
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def bmm():
+    import paper_1909_01554_amd as bmm
+    return bmm
+
+
+def transpose_packed(B, k, n):
+    from oracle import brute
+    return brute.pack(brute.unpack(B, n).T.copy())
+
+
+def make_problems(count, seed, maxdim=600, transposed=True):
+    rng = np.random.default_rng(seed)
+    probs, host = [], []
+    for p in range(count):
+        m, k, n = (int(x) for x in rng.integers(1, maxdim, size=3))
+        if p % 7 == 3:
+            k = 0
+        sr = oracle.GF2 if p % 2 == 0 else oracle.BOOLEAN
+        dist = bmmgen.Dist.half() if sr == oracle.GF2 else bmmgen.Dist.inv_sqrt(max(k, 1))
+        A = bmmgen.fill_cpu(m, max(k, 1), seed, bmmgen.batched_tag(p, "A"), dist)
+        B = bmmgen.fill_cpu(max(k, 1), n, seed, bmmgen.batched_tag(p, "B"), dist)
+        if k == 0:
+            A[:] = 0
+            B = B[:1]
+        Bd = to_dev(transpose_packed(B, max(k, 1), n)) if transposed else to_dev(B)
+        Cd = empty_dev(m, words(n), fill=-1)
+        probs.append(dict(semiring=sr, m=m, k=k, n=n, A=to_dev(A), B=Bd, C=Cd,
+                          b_transposed=transposed))
+        host.append((sr, A, B, m, k, n))
+    return probs, host
+
+
+def check(probs, host):
+    for pr, (sr, A, B, m, k, n) in zip(probs, host):
+        want = oracle.mul(A, B, max(k, 1), n, sr) if k else np.zeros((m, words(n)), np.uint64)
+        got = from_dev(pr["C"], words(n))
+        assert np.array_equal(got, want), (sr, m, k, n)
+
+
+@pytest.mark.parametrize("transposed", [True, False])
+def test_batched_mixed(bmm, transposed):
+    probs, host = make_problems(40, 7 + transposed, transposed=transposed)
+    announce("batched", transposed)
+    bmm.bmm_batched(probs)
+    check(probs, host)
+
+
+def test_batched_plan_graph_replay(bmm):
+    import torch
+    probs, host = make_problems(30, 21)
+    plan = bmm.BatchedPlan(probs)
+    s = torch.cuda.Stream()
+    announce("batched plan eager")
+    with torch.cuda.stream(s):
+        plan.launch(s.cuda_stream)
+    s.synchronize()
+    check(probs, host)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        plan.launch(s.cuda_stream)
+    for rep in range(3):
+        for pr in probs:
+            pr["C"].fill_(-1)
+        torch.cuda.synchronize()
+        announce("batched plan graph replay", rep)
+        g.replay()
+        torch.cuda.synchronize()
+        check(probs, host)
+    plan.destroy()
+
+
+@pytest.mark.parametrize("sr", [oracle.GF2, oracle.BOOLEAN])
+def test_ooc_small(bmm, sr):
+    import torch
+    m, k, n = 700, 1000, 900
+    dist = bmmgen.Dist.half() if sr == oracle.GF2 else bmmgen.Dist.pow2(4)
+    A = bmmgen.fill_cpu(m, k, 31, bmmgen.TAG_A, dist)
+    B = bmmgen.fill_cpu(k, n, 31, bmmgen.TAG_B, dist)
+    Ah = torch.from_numpy(A.view(np.int64)).pin_memory()
+    Bh = torch.from_numpy(B.view(np.int64)).pin_memory()
+    Ch = torch.full((m, words(n)), -1, dtype=torch.int64).pin_memory()
+    announce("ooc", sr)
+    secs = bmm.bmm_ooc(sr, Ah, Bh, Ch, m, k, n, block=256)
+    assert secs > 0
+    got = Ch.numpy().view(np.uint64)
+    assert np.array_equal(got, oracle.mul(A, B, k, n, sr))
+
+
+def test_ooc_rejects_pageable(bmm):
+    A = np.zeros((64, 1), np.uint64)
+    with pytest.raises(bmm.BmmError) as e:
+        bmm.bmm_ooc(0, A, A.copy(), A.copy(), 64, 64, 64)
+    assert e.value.status == -1

@@ -1,0 +1,183 @@
+"""GPU parity of the alternative-basis recursion: every stage kernel against
+the oracle's stage function, and the whole product against the plain product."""
+import numpy as np
+import pytest
+
+import bmmgen
+import oracle
+from oracle import algebra, strassen
+from gpu_util import announce, empty_dev, from_dev, to_dev, words
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def bmm():
+    import paper_1909_01554_amd as bmm
+    return bmm
+
+
+def rand_words(rows, nwords, seed):
+    return bmmgen.fill_cpu(rows, nwords * 64, seed, 0x77, bmmgen.Dist.half())
+
+
+@pytest.mark.parametrize("rows,cols", [(1, 1), (64, 64), (65, 130), (200, 1000), (128, 4096),
+                                       (1000, 70)])
+def test_transpose(bmm, rows, cols):
+    from oracle import brute
+    X = bmmgen.fill_cpu(rows, cols, rows + cols, 0x11, bmmgen.Dist.half())
+    Xd = to_dev(X)
+    Td = empty_dev(cols, words(rows) + 1, fill=-1)
+    announce("transpose", rows, cols)
+    bmm.bmm_transpose(Xd, Td, rows, cols)
+    got = from_dev(Td, words(rows))
+    want = brute.pack(brute.unpack(X, cols).T.copy())
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("depth", [1, 2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("inverse", [0, 1])
+def test_basis_change(bmm, depth, inverse):
+    rows, nw = 3 << depth, 2 << depth  # odd leaf rows, two-word leaf rows
+    X = rand_words(rows, nw, depth)
+    Xd = to_dev(X, nw + 3)
+    announce("basis", depth, inverse)
+    bmm.bmm_basis_change(Xd, rows, nw, depth, inverse=bool(inverse))
+    got = from_dev(Xd, nw)
+    prog = algebra.sinv_inv if inverse else algebra.sinv_fwd
+    assert np.array_equal(got, strassen.basis(X, depth, prog))
+
+
+@pytest.mark.parametrize("side", [0, 1])
+@pytest.mark.parametrize("levels", [1, 2])
+def test_expand(bmm, side, levels):
+    rows, nw, parents = 24, 8, 3
+    X = rand_words(rows * parents, nw, 40 + side + levels)
+    Xd = to_dev(X, nw + 2)  # pitch nw + 2, parents stacked with stride rows * pitch
+    ch = 7 ** levels
+    sub_r, sub_w = rows >> levels, nw >> levels
+    Dd = empty_dev(parents * ch * sub_r, sub_w, fill=-1)
+    announce("expand", side, levels)
+    bmm.bmm_expand(side, levels, Xd, nw + 2, rows * (nw + 2), Dd, rows, nw, parents)
+    got = from_dev(Dd).reshape(parents, ch, sub_r, sub_w)
+    for p in range(parents):
+        par = X[p * rows:(p + 1) * rows]
+        if side == 1:
+            # stored transposed: expand the real B (transpose of the stored words'
+            # quadrant grid) and compare quadrant-transposed children
+            want = expand_transposed(par, levels)
+        else:
+            want = expand_plain(par, levels)
+        for h in range(ch):
+            assert np.array_equal(got[p, h], want[h]), (p, h)
+
+
+def expand_plain(X, levels):
+    kids = strassen.expand_left(X)
+    if levels == 1:
+        return kids
+    return [g for c in kids for g in strassen.expand_left(c)]
+
+
+def swap_quadrants(X):
+    q = strassen.quadrants(X)
+    return strassen.assemble(q[0], q[2], q[1], q[3])
+
+
+def expand_transposed(X, levels):
+    """Right-operand expansion on transposed storage at the level of quadrant
+    blocks: the stored block (a, b) is B's block (b, a) transposed; children
+    of the stored matrix are the stored forms of beta's children."""
+    def one(Y):
+        # view stored quadrants as B's quadrants: B00=Y00, B01=Y10, B10=Y01, B11=Y11
+        q = strassen.quadrants(Y)
+        return [np.ascontiguousarray(t) for t in algebra.sinv_beta(q[0], q[2], q[1], q[3])]
+    kids = one(X)
+    if levels == 1:
+        return kids
+    return [g for c in kids for g in one(c)]
+
+
+@pytest.mark.parametrize("levels", [1, 2])
+def test_compress(bmm, levels):
+    rows, nw, parents = 16, 8, 2
+    ch = 7 ** levels
+    sub_r, sub_w = rows >> levels, nw >> levels
+    Q = rand_words(parents * ch * sub_r, sub_w, 90 + levels)
+    Qd = to_dev(Q)
+    Pd = empty_dev(parents * rows, nw + 1, fill=-1)
+    announce("compress", levels)
+    bmm.bmm_compress(levels, Qd, Pd, nw + 1, rows * (nw + 1), rows, nw, parents)
+    got = from_dev(Pd, nw).reshape(parents, rows, nw)
+    Qs = Q.reshape(parents, ch, sub_r, sub_w)
+    for p in range(parents):
+        if levels == 1:
+            want = strassen.compress([Qs[p, h] for h in range(7)])
+        else:
+            mids = [strassen.compress([Qs[p, 7 * h1 + h2] for h2 in range(7)]) for h1 in range(7)]
+            want = strassen.compress(mids)
+        assert np.array_equal(got[p], want)
+
+
+CASES = [  # m, k, n, depth, depth_serial
+    (512, 512, 512, 1, 0), (512, 512, 512, 3, 0), (1024, 1024, 1024, 4, 1),
+    (2048, 2048, 2048, 3, 1), (2048, 2048, 2048, 5, 2), (1024, 2048, 512, 2, 1),
+    (768, 1536, 1024, 1, 1), (4096, 4096, 4096, 6, 2), (2048, 2048, 2048, 0, 0),
+]
+
+
+@pytest.mark.parametrize("m,k,n,depth,ds", CASES)
+@pytest.mark.parametrize("leaf", [1, 2])
+def test_strassen_product(bmm, m, k, n, depth, ds, leaf):
+    seed = bmmgen.config_seed(2) + m + depth
+    A = bmmgen.fill_cpu(m, k, seed, bmmgen.TAG_A, bmmgen.Dist.half())
+    B = bmmgen.fill_cpu(k, n, seed, bmmgen.TAG_B, bmmgen.Dist.half())
+    opts = bmm.Options(leaf=leaf, depth_serial=ds, depth_parallel=depth - ds)
+    nbytes, s_, p_ = bmm.bmm_gf2_strassen_workspace(m, k, n, depth, opts)
+    assert (s_, p_) == (ds, depth - ds)
+    import torch
+    ws = torch.empty(nbytes // 8 + 1, dtype=torch.int64, device="cuda")
+    Ad, Bd = to_dev(A), to_dev(B)
+    Cd = empty_dev(m, words(n) + 1, fill=-1)
+    announce("strassen", m, k, n, depth, ds, leaf)
+    bmm.bmm_gf2_strassen(Ad, Bd, Cd, m, k, n, ws, depth=depth, options=opts)
+    got = from_dev(Cd, words(n))
+    assert np.array_equal(got, oracle.mul(A, B, k, n, oracle.GF2))
+    # inputs untouched
+    assert np.array_equal(from_dev(Ad), A) and np.array_equal(from_dev(Bd), B)
+
+
+def test_strassen_alt_basis_io(bmm):
+    """With A-hat, B-hat given, C-hat comes back (the core of eq. mb-mm-*)."""
+    m = k = n = 1024
+    d = 3
+    A = bmmgen.fill_cpu(m, k, 3, bmmgen.TAG_A, bmmgen.Dist.half())
+    B = bmmgen.fill_cpu(k, n, 3, bmmgen.TAG_B, bmmgen.Dist.half())
+    Ah = strassen.basis(A, d, algebra.sinv_fwd)
+    Bh = strassen.basis(B, d, algebra.sinv_fwd)
+    want_hat = strassen.core(Ah, Bh, d, strassen.packed_leaf(k >> d, n >> d))
+    import torch
+    opts = bmm.Options(leaf=2)
+    nbytes, _, _ = bmm.bmm_gf2_strassen_workspace(m, k, n, d, opts, alt_basis_io=True)
+    ws = torch.empty(nbytes // 8 + 1, dtype=torch.int64, device="cuda")
+    Cd = empty_dev(m, words(n))
+    announce("alt_basis_io")
+    bmm.bmm_gf2_strassen(to_dev(Ah), to_dev(Bh), Cd, m, k, n, ws, depth=d, options=opts,
+                         alt_basis_io=True)
+    assert np.array_equal(from_dev(Cd), want_hat)
+    # and the inverse basis change of C-hat gives AB
+    assert np.array_equal(strassen.basis(want_hat, d, algebra.sinv_inv),
+                          oracle.mul(A, B, k, n, oracle.GF2))
+
+
+def test_strassen_errors(bmm):
+    import torch
+    A = empty_dev(1024, 16)
+    C = empty_dev(1024, 16)
+    ws = torch.empty(16, dtype=torch.int64, device="cuda")
+    with pytest.raises(bmm.BmmError) as e:
+        bmm.bmm_gf2_strassen(A, empty_dev(1024, 16), C, 1024, 1000, 1024, ws, depth=2)
+    assert e.value.status == -2  # k not divisible by 64 * 2^d
+    with pytest.raises(bmm.BmmError) as e:
+        bmm.bmm_gf2_strassen(A, empty_dev(1024, 16), C, 1024, 1024, 1024, ws, depth=2)
+    assert e.value.status == -3  # workspace too small
