@@ -20,6 +20,7 @@ import time
 
 METRIC = "effective Pbop/s (2n^3/s), GF(2)+Boolean n=2^18: VALU vs int8-MFMA leaf"
 PEAK_MFMA_I8_TOPS = 5000.0        # dense int8 MFMA, ops/s (1 MAC = 2 ops)
+PEAK_MFMA_F4_TOPS = 10100.0       # dense fp4 (E2M1) MFMA
 # 256 CU * 128 lane-ops/clk (the fp32 vector rate: 157.3 TFLOP/s / 2) * 2.4 GHz * 32 bits
 # * 2 bit operations (AND and XOR/OR) per fused v_bitop3_b32
 PEAK_VALU_FUSED_TBOPS = 5033.2
@@ -35,14 +36,157 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=1 << 18)
-    ap.add_argument("--depth", type=int, default=6, help="Strassen levels above the leaf")
+    ap.add_argument("--depth", type=int, default=-1,
+                    help="Strassen levels above the leaf (-1: the autotune table's choice)")
+    ap.add_argument("--tune-file", default=None,
+                    help="autotune table to load (default: the package's table for gfx950)")
     ap.add_argument("--depth-serial", type=int, default=-1)
     ap.add_argument("--tile", type=int, default=0, help="MFMA leaf tile variant (0 = auto)")
     ap.add_argument("--no-valu", action="store_true", help="skip the VALU-leaf side step")
     ap.add_argument("--cpu-rows", type=int, default=256,
                     help="rows of the GF(2) product the oracle computes for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--leaf", choices=["mfma", "valu", "f4"], default="mfma",
+                    help="leaf of the timed steps (mfma = int8 MFMA, f4 = E2M1 MFMA)")
+    ap.add_argument("--no-f4", action="store_true", help="skip the fp4-leaf side step")
+    ap.add_argument("--mode", choices=["step", "leaf", "batched", "ooc", "tune"], default="step",
+                    help="leaf: one Boolean leaf launch plus a copy of known size (for "
+                         "profiler counters); batched: 4096 uneven products in one "
+                         "persistent launch; ooc: host-resident operands")
+    ap.add_argument("--problems", type=int, default=4096, help="batched mode: problem count")
+    ap.add_argument("--block", type=int, default=1 << 17, help="ooc mode: block size (bits)")
     return ap.parse_args()
+
+
+def run_batched(args, torch, np, bmm, bmmgen):
+    """4096 independent products, m, k, n log-uniform in [256, 8192] (multiples of
+    64); even problems GF(2) with Bernoulli(1/2) bits, odd problems Boolean with
+    Bernoulli(1/sqrt(k)) bits.  One persistent launch replayed from a HIP graph
+    against one launch per product."""
+    import oracle
+    dev = torch.device("cuda:0")
+    seed = bmmgen.config_seed(3)
+    rng = np.random.default_rng(seed)
+    shapes = np.exp(rng.uniform(np.log(256), np.log(8192), size=(args.problems, 3)))
+    shapes = np.clip((shapes // 64).astype(np.int64) * 64, 256, 8192)
+    words = lambda x: (int(x) + 63) // 64
+    na = sum(int(m) * words(k) for m, k, n in shapes)
+    nb = sum(int(n) * words(k) for m, k, n in shapes)
+    nc = sum(int(m) * words(n) for m, k, n in shapes)
+    log(f"[bench] batched: {args.problems} problems, operands "
+        f"{(na + nb + nc) * 8 / 2**30:.2f} GiB")
+    bufA = torch.empty(na, dtype=torch.int64, device=dev)
+    bufB = torch.empty(nb, dtype=torch.int64, device=dev)
+    bufC = torch.empty(nc, dtype=torch.int64, device=dev)
+    tmpB = torch.empty(max(int(k) * words(n) for m, k, n in shapes), dtype=torch.int64,
+                       device=dev)
+    probs, oa, ob, oc = [], 0, 0, 0
+    for p, (m, k, n) in enumerate(shapes):
+        m, k, n = int(m), int(k), int(n)
+        sr = bmm.GF2 if p % 2 == 0 else bmm.BOOLEAN
+        dist = bmmgen.Dist.half() if sr == bmm.GF2 else bmmgen.Dist.inv_sqrt(k)
+        A = bufA[oa:oa + m * words(k)].view(m, words(k))
+        BT = bufB[ob:ob + n * words(k)].view(n, words(k))
+        C = bufC[oc:oc + m * words(n)].view(m, words(n))
+        oa, ob, oc = oa + A.numel(), ob + BT.numel(), oc + C.numel()
+        bmmgen.fill_tensor(A, m, k, seed, bmmgen.batched_tag(p, "A"), dist)
+        B = tmpB[:k * words(n)].view(k, words(n))
+        bmmgen.fill_tensor(B, k, n, seed, bmmgen.batched_tag(p, "B"), dist)
+        bmm.bmm_transpose(B, BT, k, n)
+        probs.append(dict(semiring=sr, m=m, k=k, n=n, A=A, B=BT, C=C, b_transposed=True))
+    torch.cuda.synchronize()
+    bops = sum(2.0 * p["m"] * p["k"] * p["n"] for p in probs)
+    plan = bmm.BatchedPlan(probs)
+    s = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        plan.launch(s.cuda_stream)  # warm-up outside the graph
+        s.synchronize()
+        with torch.cuda.graph(g, stream=s):
+            plan.launch(s.cuda_stream)
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g.replay()
+    torch.cuda.synchronize()
+    t_graph = (time.perf_counter() - t0) / args.steps
+    opts = bmm.Options(leaf=bmm.LEAF_MFMA_I8, tile=2)
+
+    def one_by_one():
+        for p in probs:
+            fn = bmm.bmm_gf2 if p["semiring"] == bmm.GF2 else bmm.bmm_boolean
+            fn(p["A"], p["B"], p["C"], p["m"], p["k"], p["n"], options=opts, b_transposed=True)
+    one_by_one()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        one_by_one()
+    torch.cuda.synchronize()
+    t_loop = (time.perf_counter() - t0) / args.steps
+    # verify 16 problems on 8 stratified rows each against the oracle
+    ok = True
+    for p in range(0, args.problems, max(1, args.problems // 16)):
+        pr = probs[p]
+        m, k, n = pr["m"], pr["k"], pr["n"]
+        dist = bmmgen.Dist.half() if pr["semiring"] == bmm.GF2 else bmmgen.Dist.inv_sqrt(k)
+        rows = bmmgen.stratified_rows(m, 8, seed + p)
+        Ar = bmmgen.fill_rows_cpu(rows, k, seed, bmmgen.batched_tag(p, "A"), dist)
+        Bh = bmmgen.fill_cpu(k, n, seed, bmmgen.batched_tag(p, "B"), dist)
+        want = oracle.rows(Ar, Bh, k, n, pr["semiring"])
+        got = pr["C"][rows].cpu().numpy().view(np.uint64)
+        ok = ok and bool(np.array_equal(got, want))
+    plan.destroy()
+    print(json.dumps({
+        "mode": "batched", "problems": args.problems, "total_bops": bops,
+        "persistent_graph_s": round(t_graph, 5), "persistent_pbops": round(bops / t_graph / 1e15, 4),
+        "one_launch_per_product_s": round(t_loop, 5),
+        "one_launch_per_product_pbops": round(bops / t_loop / 1e15, 4),
+        "speedup": round(t_loop / t_graph, 3), "verified_16_problems": ok}), flush=True)
+
+
+def run_ooc(args, torch, np, bmm, bmmgen):
+    """GF(2) and Boolean cubic products with A, B, C in page-locked host memory,
+    streamed through HBM in blocks (double-buffered copies on their own
+    streams).  Bits: GF(2) Bernoulli(1/2), Boolean Bernoulli(2^-e) with
+    P(c = 1) ~ 0.63."""
+    import oracle
+    n = args.n
+    nw = n // 64
+    seed = bmmgen.config_seed(4)
+    out = {"mode": "ooc", "n": n, "block": args.block}
+    for name, sr, dist in [("gf2", bmm.GF2, bmmgen.Dist.half()),
+                           ("boolean", bmm.BOOLEAN,
+                            bmmgen.Dist.pow2(max(1, (n.bit_length() - 1) // 2)))]:
+        log(f"[bench] ooc {name}: generating {3 * n * nw * 8 / 2**30:.1f} GiB in pinned memory")
+        A = torch.empty((n, nw), dtype=torch.int64, pin_memory=True)
+        B = torch.empty((n, nw), dtype=torch.int64, pin_memory=True)
+        C = torch.empty((n, nw), dtype=torch.int64, pin_memory=True)
+        # generate on the GPU in row slabs and copy into the pinned buffers
+        slab = torch.empty((min(n, 1 << 15), nw), dtype=torch.int64, device="cuda")
+        for dst, tag in [(A, bmmgen.TAG_A), (B, bmmgen.TAG_B)]:
+            for r0 in range(0, n, slab.shape[0]):
+                rows = min(slab.shape[0], n - r0)
+                bmmgen.fill_tensor(slab[:rows], rows, n, seed, tag, dist, row0=r0)
+                dst[r0:r0 + rows].copy_(slab[:rows])
+        torch.cuda.synchronize()
+        secs = bmm.bmm_ooc(sr, A, B, C, n, n, n, block=args.block,
+                           options=bmm.Options(leaf=bmm.LEAF_MFMA_I8))
+        rows = bmmgen.stratified_rows(n, 16, seed)
+        Ar = bmmgen.fill_rows_cpu(rows, n, seed, bmmgen.TAG_A, dist)
+        Bh = B.numpy().view(np.uint64)
+        want = oracle.rows(Ar, Bh, n, n, sr)
+        got = C[rows].numpy().view(np.uint64)
+        blocks = (n + args.block - 1) // args.block
+        h2d = blocks ** 3 * 2 * min(args.block, n) ** 2 / 8
+        out[name] = {"seconds": round(secs, 3), "pbops": round(2.0 * n ** 3 / secs / 1e15, 4),
+                     "h2d_bytes": h2d, "pcie_inclusive_h2d_gbs": round(h2d / secs / 1e9, 2),
+                     "verified_rows": len(rows), "verified": bool(np.array_equal(got, want))}
+        log(f"[bench] ooc {name}: {secs:.2f} s {out[name]}")
+        del A, B, C, slab
+    print(json.dumps(out), flush=True)
 
 
 def main():
@@ -63,6 +207,15 @@ def main():
     import bmmgen
     import paper_1909_01554_amd as bmm
 
+    tune_file = args.tune_file or os.path.join(root, "paper_1909_01554_amd", "tune_gfx950.txt")
+    if args.mode != "tune" and os.path.exists(tune_file):
+        bmm.bmm_autotune_load(tune_file)
+        log(f"[bench] loaded autotune table {tune_file}")
+    if args.mode == "batched":
+        return run_batched(args, torch, np, bmm, bmmgen)
+    if args.mode == "ooc":
+        return run_ooc(args, torch, np, bmm, bmmgen)
+
     n = args.n
     nw = n // 64
     dev = torch.device("cuda:0")
@@ -81,19 +234,72 @@ def main():
     bmmgen.fill_tensor(Ab, n, n, seed, 0x1A, bool_dist)
     bmmgen.fill_tensor(Bb, n, n, seed, 0x1B, bool_dist)
 
+    stream = torch.cuda.current_stream()
+    LEAF = {"mfma": bmm.LEAF_MFMA_I8, "valu": bmm.LEAF_VALU, "f4": bmm.LEAF_MFMA_F4}
+
+    def events():
+        return [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+
     def opts(leaf):
-        return bmm.Options(leaf=leaf, tile=args.tile if leaf == bmm.LEAF_MFMA_I8 else 0,
+        return bmm.Options(leaf=leaf, tile=args.tile if leaf != bmm.LEAF_VALU else 0,
                            depth_serial=args.depth_serial,
                            depth_parallel=-1 if args.depth_serial < 0 else
                            args.depth - args.depth_serial)
 
+    if args.mode == "leaf":
+        bmm.bmm_transpose(Bb, BTb, n, n)
+        src = torch.empty(1 << 29, dtype=torch.int64, device=dev)  # 4 GiB
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        e = events()
+        e[0].record(stream)
+        bmm.bmm_boolean(Ab, BTb, Cb, n, n, n, options=bmm.Options(leaf=LEAF[args.leaf],
+                        tile=args.tile), b_transposed=True)
+        e[1].record(stream)
+        dst.copy_(src)
+        e[2].record(stream)
+        torch.cuda.synchronize()
+        print(json.dumps({"mode": "leaf", "n": n, "leaf": args.leaf,
+                          "leaf_s": e[0].elapsed_time(e[1]) / 1e3,
+                          "copy_bytes": 2 * src.numel() * 8,
+                          "copy_s": e[1].elapsed_time(e[2]) / 1e3}), flush=True)
+        return
+
     nbytes, ds, dp = bmm.bmm_gf2_strassen_workspace(n, n, n, args.depth, opts(bmm.LEAF_MFMA_I8))
+    if args.mode == "tune":
+        # room for the deeper plans the depth tuner tries
+        nbytes = max(nbytes, bmm.bmm_gf2_strassen_workspace(
+            n, n, n, 6, bmm.Options(depth_serial=2, depth_parallel=4))[0])
     ws = torch.empty(nbytes // 8 + 1, dtype=torch.int64, device=dev)
+    if args.mode == "tune":
+        out = {"mode": "tune", "n": n}
+        # leaf table: the Boolean cubic shape (timed on a 16384-row proxy with the full k)
+        # and the Strassen leaf shapes of the admissible depths (batches of 64)
+        proxy = min(n, 16384)
+        for sr, name in [(bmm.BOOLEAN, "boolean"), (bmm.GF2, "gf2")]:
+            leaf, tile, secs = bmm.bmm_autotune_leaf(sr, proxy, n, proxy, 1)
+            bmm.bmm_autotune_set(sr, n, n, n, leaf, tile, batch=1)
+            out[f"cubic_{name}"] = {"leaf": leaf, "tile": tile, "proxy_s": secs}
+            log(f"[bench] tuned cubic {name} leaf={leaf} tile={tile}")
+        for d in range(4, 9):
+            s_ = n >> d
+            if s_ < 1024:
+                break
+            leaf, tile, secs = bmm.bmm_autotune_leaf(bmm.GF2, s_, s_, s_, 2401)
+            out[f"strassen_leaf_{s_}"] = {"leaf": leaf, "tile": tile, "s": secs}
+            log(f"[bench] tuned leaf {s_}^3 x64: leaf={leaf} tile={tile} {secs * 1e3:.2f} ms")
+        # the depth tuner times the int8-MFMA leaf (the headline leaf)
+        d, dsel, secs = bmm.bmm_autotune_strassen(Ag, Bg, Cg, n, n, n, ws,
+                                                  options=bmm.Options(leaf=bmm.LEAF_MFMA_I8))
+        out["strassen_depth"] = {"depth": d, "depth_serial": dsel, "seconds": secs}
+        log(f"[bench] tuned Strassen depth {d} (serial {dsel}) {secs:.3f} s")
+        bmm.bmm_autotune_save(tune_file)
+        out["table"] = tune_file
+        print(json.dumps(out), flush=True)
+        return
     log(f"[bench] Strassen depth {args.depth} (serial {ds}, parallel {dp}), workspace "
         f"{nbytes / 2**30:.1f} GiB")
     torch.cuda.synchronize()
-
-    stream = torch.cuda.current_stream()
 
     def step(leaf, ev=None):
         o = opts(leaf)
@@ -109,19 +315,16 @@ def main():
         if ev:
             ev[3].record(stream)
 
-    def events():
-        return [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-
     for w in range(args.warmup):
         log(f"[bench] warmup step {w}")
-        step(bmm.LEAF_MFMA_I8)
+        step(LEAF[args.leaf])
         torch.cuda.synchronize()
 
     evs = [events() for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        step(bmm.LEAF_MFMA_I8, evs[i])
+        step(LEAF[args.leaf], evs[i])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     step_s = (t1 - t0) / args.steps
@@ -132,21 +335,26 @@ def main():
     log(f"[bench] MFMA step {step_s:.3f} s: GF(2) Strassen {gf2_s:.3f} s, transpose {tr_s * 1e3:.2f}"
         f" ms, Boolean leaf {leaf_s:.3f} s")
 
-    valu = None
-    if not args.no_valu:
-        log("[bench] VALU-leaf step")
+    def side_step(name, peak_tbops):
+        log(f"[bench] {name}-leaf step")
         e = events()
-        step(bmm.LEAF_VALU, e)
+        step(LEAF[name], e)
         torch.cuda.synchronize()
         vg = e[0].elapsed_time(e[1]) / 1e3
         vb = e[2].elapsed_time(e[3]) / 1e3
         vt = e[0].elapsed_time(e[3]) / 1e3
-        valu = {"step_s": round(vt, 4), "value": round(2 * bops / vt / 1e15, 4),
+        log(f"[bench] {name} step {vt:.3f} s (GF(2) {vg:.3f} s, Boolean {vb:.3f} s)")
+        return {"step_s": round(vt, 4), "value": round(2 * bops / vt / 1e15, 4),
                 "gf2_strassen_s": round(vg, 4), "gf2_eff_pbops": round(bops / vg / 1e15, 4),
                 "boolean_s": round(vb, 4), "boolean_pbops": round(bops / vb / 1e15, 4),
-                "boolean_leaf_frac_of_fused_valu_peak":
-                    round(bops / vb / 1e12 / PEAK_VALU_FUSED_TBOPS, 4)}
-        log(f"[bench] VALU step {vt:.3f} s (GF(2) {vg:.3f} s, Boolean {vb:.3f} s)")
+                "boolean_leaf_frac_of_peak": round(bops / vb / 1e12 / peak_tbops, 4)}
+
+    valu = None
+    if not args.no_valu and args.leaf != "valu":
+        valu = side_step("valu", PEAK_VALU_FUSED_TBOPS)
+    f4 = None
+    if not args.no_f4 and args.leaf != "f4":
+        f4 = side_step("f4", PEAK_MFMA_F4_TOPS)
 
     # Rows of both products, checked against the oracle; the GF(2) rows time the oracle.
     cpu = None
@@ -182,6 +390,8 @@ def main():
 
     value = 2 * bops / step_s / 1e15
     achieved = bops / leaf_s / 1e12  # TOP/s of the Boolean leaf launch
+    peak = {"mfma": PEAK_MFMA_I8_TOPS, "f4": PEAK_MFMA_F4_TOPS,
+            "valu": PEAK_VALU_FUSED_TBOPS}[args.leaf]
     line = {
         "metric": METRIC,
         "value": round(value, 4),
@@ -199,14 +409,18 @@ def main():
             "workload": f"GF(2) alt-basis Strassen + Boolean cubic product, n={n} square",
             "n": n, "gf2_bits": "Bernoulli(1/2)", "boolean_bits": f"Bernoulli({bool_dist.p:g})",
             "strassen_depth": args.depth, "depth_serial": ds, "depth_parallel": dp,
-            "leaf": "int8 MFMA", "gf2_strassen_s": round(gf2_s, 4),
+            "leaf": {"mfma": "int8 MFMA", "f4": "fp4 MFMA", "valu": "VALU bitop3"}[args.leaf],
+            "gf2_strassen_s": round(gf2_s, 4),
             "gf2_eff_pbops": round(bops / gf2_s / 1e15, 4),
             "boolean_s": round(leaf_s + tr_s, 4), "boolean_pbops": round(bops / leaf_s / 1e15, 4),
         },
         "valu_leaf": valu,
-        "roofline": {"bound": "mfma", "kernel": "leaf_mfma_kernel (Boolean, one launch)",
-                     "achieved": round(achieved, 1), "peak": PEAK_MFMA_I8_TOPS,
-                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_MFMA_I8_TOPS, 4),
+        "f4_leaf": f4,
+        "roofline": {"bound": "alu" if args.leaf == "valu" else "mfma",
+                     "kernel": ("leaf_valu_kernel" if args.leaf == "valu" else "leaf_mfma_kernel")
+                               + " (Boolean cubic product, one launch per step)",
+                     "achieved": round(achieved, 1), "peak": peak,
+                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
                      "traffic": None},
         "cpu_baseline": cpu,
         "verified": verified,

@@ -56,9 +56,11 @@ typedef enum { BMM_GF2 = 0, BMM_BOOLEAN = 1 } bmm_semiring;
 
 /* Leaf kernels for the cubic product. */
 typedef enum {
-  BMM_LEAF_AUTO = 0,   /* autotuner's choice */
-  BMM_LEAF_VALU = 1,   /* bitwise vector ALU leaf (v_bitop3_b32) */
-  BMM_LEAF_MFMA_I8 = 2 /* int8 matrix-core leaf, exact int32 counts */
+  BMM_LEAF_AUTO = 0,    /* autotuner's choice */
+  BMM_LEAF_VALU = 1,    /* bitwise vector ALU leaf (v_bitop3_b32) */
+  BMM_LEAF_MFMA_I8 = 2, /* int8 matrix-core leaf, exact int32 counts */
+  BMM_LEAF_MFMA_F4 = 3  /* E2M1 (fp4) matrix-core leaf, exact fp32 counts; k < 2^24,
+                           else BMM_E_UNSUPPORTED */
 } bmm_leaf;
 
 /* Flags. */
@@ -186,13 +188,26 @@ int bmm_compress(int levels, const uint64_t* src, uint64_t* dst, int64_t ldp, in
 int bmm_leaf_tiles(int leaf, int* count_out);
 int bmm_leaf_tile_shape(int leaf, int tile, int* rows_out, int* cols_out);
 
-/* Autotuner: time the candidate leaf kernels / Strassen splits for a shape on
- * the current device (synchronizes; allocates scratch) and remember the best in
- * the in-process table that BMM_LEAF_AUTO and depth -1 consult.  The table can
- * be saved and loaded as text. */
+/* Autotuner (the paper fixes its layer depths empirically under memory limits,
+ * section 3.17).  Leaf table: bmm_autotune_leaf times every leaf kernel and tile
+ * on `batch` independent m x k x n products (batch bucketed to 1, 2, 4, ..., 64;
+ * allocates and frees scratch, synchronizes) and records the fastest for
+ * BMM_LEAF_AUTO / tile 0; bmm_autotune_cubic is the batch-1 case;
+ * bmm_autotune_set records an entry by hand.  Depth table:
+ * bmm_autotune_strassen times bmm_gf2_strassen on the caller's operands for the
+ * deepest four admissible depths (leaves >= 1024 bits), each with the fewest
+ * depth-first levels whose workspace fits, and records the fastest for depth -1.
+ * Both tables are per process and can be saved to / loaded from a text file. */
+int bmm_autotune_leaf(int semiring, int64_t m, int64_t k, int64_t n, int64_t batch,
+                      int* leaf_out, int* tile_out, double* seconds_out);
 int bmm_autotune_cubic(int semiring, int64_t m, int64_t k, int64_t n, int* leaf_out,
                        int* tile_out, double* seconds_out);
-int bmm_autotune_set(int semiring, int64_t m, int64_t k, int64_t n, int leaf, int tile);
+int bmm_autotune_set(int semiring, int64_t m, int64_t k, int64_t n, int64_t batch, int leaf,
+                     int tile);
+int bmm_autotune_strassen(const uint64_t* A, int64_t lda, const uint64_t* B, int64_t ldb,
+                          uint64_t* C, int64_t ldc, int64_t m, int64_t k, int64_t n,
+                          void* workspace, size_t workspace_bytes, const bmm_options* opt,
+                          int* depth_out, int* depth_serial_out, double* seconds_out);
 int bmm_autotune_save(const char* path);
 int bmm_autotune_load(const char* path);
 

@@ -16,16 +16,18 @@ from . import build as _build
 
 __all__ = [
     "BmmError", "Options", "GF2", "BOOLEAN", "LEAF_AUTO", "LEAF_VALU", "LEAF_MFMA_I8",
+    "LEAF_MFMA_F4",
     "FLAG_ACCUMULATE", "FLAG_B_TRANSPOSED", "FLAG_ALT_BASIS_IO", "FLAG_HOST_OPERANDS",
     "words", "bmm_gf2", "bmm_boolean", "bmm_gf2_strassen", "bmm_gf2_strassen_workspace",
     "bmm_batched", "BatchedPlan", "bmm_transpose", "bmm_basis_change", "bmm_expand",
-    "bmm_compress", "bmm_ooc", "bmm_autotune_cubic", "bmm_autotune_set", "bmm_autotune_save",
+    "bmm_compress", "bmm_ooc", "bmm_autotune_cubic", "bmm_autotune_leaf",
+    "bmm_autotune_strassen", "bmm_autotune_set", "bmm_autotune_save",
     "bmm_autotune_load", "bmm_leaf_tiles", "bmm_leaf_tile_shape", "bmm_version",
     "bmm_finalize", "library_path",
 ]
 
 GF2, BOOLEAN = 0, 1
-LEAF_AUTO, LEAF_VALU, LEAF_MFMA_I8 = 0, 1, 2
+LEAF_AUTO, LEAF_VALU, LEAF_MFMA_I8, LEAF_MFMA_F4 = 0, 1, 2, 3
 FLAG_ACCUMULATE = 0x1
 FLAG_B_TRANSPOSED = 0x2
 FLAG_ALT_BASIS_IO = 0x4
@@ -100,7 +102,13 @@ _c_ooc = _sig("bmm_ooc", [_int, _vp, _i64, _vp, _i64, _vp, _i64, _i64, _i64, _i6
                           ctypes.POINTER(Options), ctypes.POINTER(ctypes.c_double)])
 _c_tune = _sig("bmm_autotune_cubic", [_int, _i64, _i64, _i64, ctypes.POINTER(_int),
                                       ctypes.POINTER(_int), ctypes.POINTER(ctypes.c_double)])
-_c_tune_set = _sig("bmm_autotune_set", [_int, _i64, _i64, _i64, _int, _int])
+_c_tune_set = _sig("bmm_autotune_set", [_int, _i64, _i64, _i64, _i64, _int, _int])
+_c_tune_leaf = _sig("bmm_autotune_leaf", [_int, _i64, _i64, _i64, _i64, ctypes.POINTER(_int),
+                                          ctypes.POINTER(_int), ctypes.POINTER(ctypes.c_double)])
+_c_tune_strassen = _sig("bmm_autotune_strassen",
+                        [_vp, _i64, _vp, _i64, _vp, _i64, _i64, _i64, _i64, _vp,
+                         ctypes.c_size_t, ctypes.POINTER(Options), ctypes.POINTER(_int),
+                         ctypes.POINTER(_int), ctypes.POINTER(ctypes.c_double)])
 _c_tune_save = _sig("bmm_autotune_save", [ctypes.c_char_p])
 _c_tune_load = _sig("bmm_autotune_load", [ctypes.c_char_p])
 _c_tiles = _sig("bmm_leaf_tiles", [_int, ctypes.POINTER(_int)])
@@ -288,8 +296,32 @@ def bmm_autotune_cubic(semiring, m, k, n):
     return leaf.value, tile.value, secs.value
 
 
-def bmm_autotune_set(semiring, m, k, n, leaf, tile):
-    _check(_c_tune_set(semiring, m, k, n, leaf, tile))
+def bmm_autotune_leaf(semiring, m, k, n, batch=1):
+    """Time every leaf kernel and tile on `batch` products; returns (leaf, tile, seconds)."""
+    leaf = _int(0)
+    tile = _int(0)
+    secs = ctypes.c_double(0.0)
+    _check(_c_tune_leaf(semiring, m, k, n, batch, ctypes.byref(leaf), ctypes.byref(tile),
+                        ctypes.byref(secs)))
+    return leaf.value, tile.value, secs.value
+
+
+def bmm_autotune_strassen(A, B, C, m, k, n, workspace, options=None):
+    """Time the admissible Strassen depths on these operands; returns
+    (depth, depth_serial, seconds) and records them for depth -1."""
+    o = _opts(options, 0)
+    d = _int(0)
+    ds = _int(0)
+    secs = ctypes.c_double(0.0)
+    nbytes = workspace.numel() * workspace.element_size()
+    _check(_c_tune_strassen(_ptr(A), _ld(A), _ptr(B), _ld(B), _ptr(C), _ld(C), m, k, n,
+                            _ptr(workspace), nbytes, ctypes.byref(o), ctypes.byref(d),
+                            ctypes.byref(ds), ctypes.byref(secs)))
+    return d.value, ds.value, secs.value
+
+
+def bmm_autotune_set(semiring, m, k, n, leaf, tile, batch=1):
+    _check(_c_tune_set(semiring, m, k, n, batch, leaf, tile))
 
 
 def bmm_autotune_save(path):

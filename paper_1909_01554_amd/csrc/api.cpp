@@ -101,32 +101,48 @@ int scratch(size_t bytes, void** out) {
 }
 
 // ---- autotune table ----
+// Keyed by semiring, leaf shape and batch bucket (1, 2, 4, ..., 64 = "64 or more").
 struct TuneKey {
   int semiring;
-  int64_t m, k, n;
+  int64_t m, k, n, batch;
   bool operator<(const TuneKey& o) const {
-    return std::tie(semiring, m, k, n) < std::tie(o.semiring, o.m, o.k, o.n);
+    return std::tie(semiring, m, k, n, batch) < std::tie(o.semiring, o.m, o.k, o.n, o.batch);
   }
 };
-std::map<TuneKey, std::pair<int, int>> g_tune;
+// Per key: the fastest leaf kind and the fastest tile of every leaf kind (0 = unknown).
+struct TuneVal {
+  int best_leaf = 0;
+  int tile[4] = {0, 0, 0, 0};
+};
+std::map<TuneKey, TuneVal> g_tune;
+// Strassen (depth, serial depth) per shape, from bmm_autotune_strassen.
+std::map<std::tuple<int64_t, int64_t, int64_t>, std::pair<int, int>> g_depth;
 
-void pick_leaf(int semiring, int64_t m, int64_t k, int64_t n, const bmm_options& o, int* leaf,
-               int* tile) {
+int64_t batch_bucket(int64_t b) {
+  int64_t q = 1;
+  while (q < b && q < 64) q <<= 1;
+  return q;
+}
+
+void pick_leaf(int semiring, int64_t m, int64_t k, int64_t n, int64_t batch,
+               const bmm_options& o, int* leaf, int* tile) {
   *leaf = o.leaf;
   *tile = o.tile;
   if (*leaf == BMM_LEAF_AUTO || *tile <= 0) {
     std::lock_guard<std::mutex> lock(g_mu);
-    auto it = g_tune.find({semiring, m, k, n});
+    auto it = g_tune.find({semiring, m, k, n, batch_bucket(batch)});
     if (it != g_tune.end()) {
-      if (*leaf == BMM_LEAF_AUTO) *leaf = it->second.first;
-      if (*tile <= 0 && *leaf == it->second.first) *tile = it->second.second;
+      if (*leaf == BMM_LEAF_AUTO && it->second.best_leaf > 0) *leaf = it->second.best_leaf;
+      if (*tile <= 0 && *leaf >= 1 && *leaf <= 3) *tile = it->second.tile[*leaf];
     }
   }
   if (*leaf == BMM_LEAF_AUTO) *leaf = BMM_LEAF_MFMA_I8;
   if (*tile <= 0) {
-    // default MFMA tile: 128 x 64 per wave; small problems use 64 x 64 to fill the chip
+    // default MFMA tile: 128 x 64 per wave; when that gives fewer than 16 waves per
+    // CU over the whole launch, 64 x 64 tiles fill the chip better
     *tile = 1;
-    if (*leaf == BMM_LEAF_MFMA_I8 && m * n < (int64_t)8192 * 8192) *tile = 2;
+    const int64_t waves = batch * ((m + 127) / 128) * ((n + 63) / 64);
+    if (*leaf != BMM_LEAF_VALU && waves < 4096) *tile = 2;
   }
 }
 
@@ -136,6 +152,10 @@ int run_leaf(int semiring, int leaf, int tile, const LeafBatch& p, hipStream_t s
     e = launch_leaf_valu(semiring, p, tile - 1, s);
   } else if (leaf == BMM_LEAF_MFMA_I8) {
     e = launch_leaf_mfma(semiring, p, tile - 1, s);
+  } else if (leaf == BMM_LEAF_MFMA_F4) {
+    if (p.k >= ((int64_t)1 << 24))
+      return fail(BMM_E_UNSUPPORTED, "the fp4 leaf counts exactly only for k < 2^24");
+    e = launch_leaf_mfma_f4(semiring, p, tile - 1, s);
   } else {
     return fail(BMM_E_INVAL, "unknown leaf %d", leaf);
   }
@@ -190,7 +210,7 @@ int cubic(int semiring, const uint64_t* A, int64_t lda, const uint64_t* B, int64
     ldbt = kw;
   }
   int leaf, tile;
-  pick_leaf(semiring, m, k, n, o, &leaf, &tile);
+  pick_leaf(semiring, m, k, n, 1, o, &leaf, &tile);
   LeafBatch p{A, lda, 0, BT, ldbt, 0, C, ldc, 0, m, k, n, 1, acc ? 1 : 0};
   return run_leaf(semiring, leaf, tile, p, s);
 }
@@ -221,6 +241,15 @@ int make_plan(int64_t m, int64_t k, int64_t n, int depth, const bmm_options& o, 
   P.kw = words_of(k);
   P.n = n;
   P.nw = words_of(n);
+  int tuned_ds = -1;
+  if (depth == -1) {
+    std::lock_guard<std::mutex> lock(g_mu);
+    auto it = g_depth.find({m, k, n});
+    if (it != g_depth.end()) {
+      depth = it->second.first;
+      tuned_ds = it->second.second;
+    }
+  }
   if (depth == -1) {
     // largest depth keeping every leaf dimension >= 4096 bits (at most 8 levels)
     depth = 0;
@@ -238,7 +267,10 @@ int make_plan(int64_t m, int64_t k, int64_t n, int depth, const bmm_options& o, 
                 "Strassen depth %d needs m %% 2^d == 0 and k, n %% (64 * 2^d) == 0", depth);
   P.depth = depth;
   int dp = o.depth_parallel, ds = o.depth_serial;
-  if (dp < 0 && ds < 0) {
+  if (dp < 0 && ds < 0 && tuned_ds >= 0 && tuned_ds <= depth) {
+    ds = tuned_ds;
+    dp = depth - ds;
+  } else if (dp < 0 && ds < 0) {
     dp = std::min(depth, 4);
     ds = depth - dp;
   } else if (dp < 0) {
@@ -461,7 +493,9 @@ int bmm_gf2_strassen(const uint64_t* A, int64_t lda, const uint64_t* B, int64_t 
   }
   int leaf, tile;
   const int64_t u = (int64_t)1 << P.depth;
-  pick_leaf(BMM_GF2, m / u, k / u, n / u, o, &leaf, &tile);
+  int64_t leaves = 1;
+  for (int i = 0; i < P.dp; ++i) leaves *= 7;
+  pick_leaf(BMM_GF2, m / u, k / u, n / u, leaves, o, &leaf, &tile);
   StrassenRun run{&P, ws, leaf, tile, s};
   BMM_TRY(run.solve(0, T0, ldT0, BT, P.kw, C, ldc));
   if (!alt) HIP_TRY(launch_basis(C, ldc, 0, m, P.nw, 1, P.depth, 1, s), "basis C");
@@ -527,7 +561,7 @@ int bmm_compress(int levels, const uint64_t* src, uint64_t* dst, int64_t ldp, in
 int bmm_leaf_tiles(int leaf, int* count_out) {
   if (!count_out) return fail(BMM_E_INVAL, "null count_out");
   if (leaf == BMM_LEAF_VALU) *count_out = 1;
-  else if (leaf == BMM_LEAF_MFMA_I8) *count_out = MFMA_NUM_TILES;
+  else if (leaf == BMM_LEAF_MFMA_I8 || leaf == BMM_LEAF_MFMA_F4) *count_out = MFMA_NUM_TILES;
   else return fail(BMM_E_INVAL, "unknown leaf %d", leaf);
   return BMM_OK;
 }
@@ -539,7 +573,8 @@ int bmm_leaf_tile_shape(int leaf, int tile, int* rows_out, int* cols_out) {
     *cols_out = 128;
     return BMM_OK;
   }
-  if (leaf == BMM_LEAF_MFMA_I8 && tile >= 1 && tile <= MFMA_NUM_TILES) {
+  if ((leaf == BMM_LEAF_MFMA_I8 || leaf == BMM_LEAF_MFMA_F4) && tile >= 1 &&
+      tile <= MFMA_NUM_TILES) {
     *rows_out = leaf_mfma_tile_rows(tile - 1);
     *cols_out = leaf_mfma_tile_cols(tile - 1);
     return BMM_OK;
@@ -547,72 +582,159 @@ int bmm_leaf_tile_shape(int leaf, int tile, int* rows_out, int* cols_out) {
   return fail(BMM_E_INVAL, "unknown leaf %d / tile %d", leaf, tile);
 }
 
-int bmm_autotune_set(int semiring, int64_t m, int64_t k, int64_t n, int leaf, int tile) {
+int bmm_autotune_set(int semiring, int64_t m, int64_t k, int64_t n, int64_t batch, int leaf,
+                     int tile) {
   int count = 0;
   if (semiring != BMM_GF2 && semiring != BMM_BOOLEAN) return fail(BMM_E_INVAL, "bad semiring");
+  if (m <= 0 || k < 0 || n <= 0 || batch <= 0) return fail(BMM_E_INVAL, "bad shape");
   BMM_TRY(bmm_leaf_tiles(leaf, &count));
   if (tile < 1 || tile > count) return fail(BMM_E_INVAL, "bad tile %d", tile);
   std::lock_guard<std::mutex> lock(g_mu);
-  g_tune[{semiring, m, k, n}] = {leaf, tile};
+  TuneVal& v = g_tune[{semiring, m, k, n, batch_bucket(batch)}];
+  v.best_leaf = leaf;
+  v.tile[leaf] = tile;
   return BMM_OK;
 }
 
-int bmm_autotune_cubic(int semiring, int64_t m, int64_t k, int64_t n, int* leaf_out,
-                       int* tile_out, double* seconds_out) {
+int bmm_autotune_leaf(int semiring, int64_t m, int64_t k, int64_t n, int64_t batch,
+                      int* leaf_out, int* tile_out, double* seconds_out) {
   if (semiring != BMM_GF2 && semiring != BMM_BOOLEAN) return fail(BMM_E_INVAL, "bad semiring");
-  if (m <= 0 || k <= 0 || n <= 0) return fail(BMM_E_INVAL, "sizes must be positive");
+  if (m <= 0 || k <= 0 || n <= 0 || batch <= 0) return fail(BMM_E_INVAL, "sizes must be positive");
   const int64_t kw = words_of(k), nw = words_of(n);
+  const int64_t nb = batch_bucket(batch);  // time on the bucket's batch size
   uint64_t *A = nullptr, *BT = nullptr, *C = nullptr;
   const size_t ba = (size_t)m * kw * 8, bb = (size_t)n * kw * 8, bc = (size_t)m * nw * 8;
-  if (hipMalloc((void**)&A, ba) != hipSuccess || hipMalloc((void**)&BT, bb) != hipSuccess ||
-      hipMalloc((void**)&C, bc) != hipSuccess) {
+  if (hipMalloc((void**)&A, ba * nb) != hipSuccess || hipMalloc((void**)&BT, bb * nb) != hipSuccess ||
+      hipMalloc((void**)&C, bc * nb) != hipSuccess) {
     (void)hipGetLastError();
-    hipFree(A);
-    hipFree(BT);
-    hipFree(C);
+    (void)hipFree(A);
+    (void)hipFree(BT);
+    (void)hipFree(C);
     return fail(BMM_E_NOMEM, "autotune buffers");
   }
   int rc = BMM_OK;
   double best = 1e30;
   int best_leaf = BMM_LEAF_MFMA_I8, best_tile = 1;
+  double best_of[4] = {1e30, 1e30, 1e30, 1e30};
+  int tile_of[4] = {0, 0, 0, 0};
   hipEvent_t e0, e1;
-  hipEventCreate(&e0);
-  hipEventCreate(&e1);
-  hipMemsetD32((hipDeviceptr_t)A, 0x5A5A5A5A, ba / 4);
-  hipMemsetD32((hipDeviceptr_t)BT, 0x3C3C3C3C, bb / 4);
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  (void)hipMemsetD32((hipDeviceptr_t)A, 0x5A5A5A5A, ba * nb / 4);
+  (void)hipMemsetD32((hipDeviceptr_t)BT, 0x3C3C3C3C, bb * nb / 4);
   std::vector<std::pair<int, int>> cands = {{BMM_LEAF_VALU, 1}};
   for (int t = 1; t <= MFMA_NUM_TILES; ++t) cands.push_back({BMM_LEAF_MFMA_I8, t});
+  if (k < ((int64_t)1 << 24))
+    for (int t = 1; t <= MFMA_NUM_TILES; ++t) cands.push_back({BMM_LEAF_MFMA_F4, t});
   for (auto [leaf, tile] : cands) {
-    LeafBatch p{A, kw, 0, BT, kw, 0, C, nw, 0, m, k, n, 1, 0};
+    LeafBatch p{A, kw, m * kw, BT, kw, n * kw, C, nw, m * nw, m, k, n, nb, 0};
     rc = run_leaf(semiring, leaf, tile, p, nullptr);  // warm-up
     if (rc != BMM_OK) break;
     const int reps = 3;
-    hipEventRecord(e0, nullptr);
+    (void)hipEventRecord(e0, nullptr);
     for (int r = 0; r < reps && rc == BMM_OK; ++r) rc = run_leaf(semiring, leaf, tile, p, nullptr);
-    hipEventRecord(e1, nullptr);
+    (void)hipEventRecord(e1, nullptr);
     if (rc != BMM_OK) break;
     if (hipEventSynchronize(e1) != hipSuccess) {
       rc = check_hip(hipGetLastError(), "autotune sync");
       break;
     }
     float ms = 0.f;
-    hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventElapsedTime(&ms, e0, e1);
     const double sec = ms * 1e-3 / reps;
+    if (sec < best_of[leaf]) {
+      best_of[leaf] = sec;
+      tile_of[leaf] = tile;
+    }
     if (sec < best) {
       best = sec;
       best_leaf = leaf;
       best_tile = tile;
     }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
-  hipFree(A);
-  hipFree(BT);
-  hipFree(C);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(A);
+  (void)hipFree(BT);
+  (void)hipFree(C);
   if (rc != BMM_OK) return rc;
-  BMM_TRY(bmm_autotune_set(semiring, m, k, n, best_leaf, best_tile));
+  {
+    std::lock_guard<std::mutex> lock(g_mu);
+    TuneVal& v = g_tune[{semiring, m, k, n, nb}];
+    v.best_leaf = best_leaf;
+    for (int l = 1; l <= 3; ++l)
+      if (tile_of[l]) v.tile[l] = tile_of[l];
+  }
   if (leaf_out) *leaf_out = best_leaf;
   if (tile_out) *tile_out = best_tile;
+  if (seconds_out) *seconds_out = best;
+  return BMM_OK;
+}
+
+int bmm_autotune_cubic(int semiring, int64_t m, int64_t k, int64_t n, int* leaf_out,
+                       int* tile_out, double* seconds_out) {
+  return bmm_autotune_leaf(semiring, m, k, n, 1, leaf_out, tile_out, seconds_out);
+}
+
+int bmm_autotune_strassen(const uint64_t* A, int64_t lda, const uint64_t* B, int64_t ldb,
+                          uint64_t* C, int64_t ldc, int64_t m, int64_t k, int64_t n,
+                          void* workspace, size_t workspace_bytes, const bmm_options* opt,
+                          int* depth_out, int* depth_serial_out, double* seconds_out) {
+  const bmm_options o = opt ? *opt : defaults();
+  int dmax = 0;
+  while (dmax < 10) {
+    const int64_t u = (int64_t)2 << dmax;
+    if (m % u || k % (64 * u) || n % (64 * u) || m / u < 1024 || k / u < 1024 || n / u < 1024)
+      break;
+    ++dmax;
+  }
+  hipEvent_t e0, e1;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  double best = 1e30;
+  int best_d = -1, best_ds = -1, rc = BMM_OK, tried = 0;
+  for (int d = dmax; d >= std::max(0, dmax - 3); --d) {
+    for (int ds = 0; ds <= d; ++ds) {
+      bmm_options t = o;
+      t.depth_serial = ds;
+      t.depth_parallel = d - ds;
+      size_t need = 0;
+      if (bmm_gf2_strassen_workspace(m, k, n, d, &t, &need, nullptr, nullptr) != BMM_OK) continue;
+      if (need > workspace_bytes) continue;  // more breadth-first levels than memory allows
+      rc = bmm_gf2_strassen(A, lda, B, ldb, C, ldc, m, k, n, d, workspace, workspace_bytes, &t,
+                            nullptr);
+      if (rc != BMM_OK) break;
+      (void)hipEventRecord(e0, nullptr);
+      rc = bmm_gf2_strassen(A, lda, B, ldb, C, ldc, m, k, n, d, workspace, workspace_bytes, &t,
+                            nullptr);
+      (void)hipEventRecord(e1, nullptr);
+      if (rc != BMM_OK) break;
+      if (hipEventSynchronize(e1) != hipSuccess) {
+        rc = check_hip(hipGetLastError(), "autotune sync");
+        break;
+      }
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      ++tried;
+      if (ms * 1e-3 < best) {
+        best = ms * 1e-3;
+        best_d = d;
+        best_ds = ds;
+      }
+      break;  // the fewest serial levels that fit is the candidate for this depth
+    }
+    if (rc != BMM_OK) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != BMM_OK) return rc;
+  if (!tried) return fail(BMM_E_WORKSPACE, "no Strassen depth fits the workspace");
+  {
+    std::lock_guard<std::mutex> lock(g_mu);
+    g_depth[{m, k, n}] = {best_d, best_ds};
+  }
+  if (depth_out) *depth_out = best_d;
+  if (depth_serial_out) *depth_serial_out = best_ds;
   if (seconds_out) *seconds_out = best;
   return BMM_OK;
 }
@@ -622,10 +744,16 @@ int bmm_autotune_save(const char* path) {
   std::ofstream f(path);
   if (!f) return fail(BMM_E_INVAL, "cannot write %s", path);
   std::lock_guard<std::mutex> lock(g_mu);
-  f << "# bmm autotune table: semiring m k n leaf tile\n";
+  f << "# bmm autotune table\n"
+       "# leaf semiring m k n batch_bucket best_leaf tile_valu tile_mfma_i8 tile_mfma_f4\n"
+       "# depth m k n depth depth_serial\n";
   for (auto& [key, val] : g_tune)
-    f << key.semiring << ' ' << key.m << ' ' << key.k << ' ' << key.n << ' ' << val.first << ' '
-      << val.second << '\n';
+    f << "leaf " << key.semiring << ' ' << key.m << ' ' << key.k << ' ' << key.n << ' '
+      << key.batch << ' ' << val.best_leaf << ' ' << val.tile[1] << ' ' << val.tile[2] << ' '
+      << val.tile[3] << '\n';
+  for (auto& [key, val] : g_depth)
+    f << "depth " << std::get<0>(key) << ' ' << std::get<1>(key) << ' ' << std::get<2>(key)
+      << ' ' << val.first << ' ' << val.second << '\n';
   return f ? BMM_OK : fail(BMM_E_INVAL, "write failed: %s", path);
 }
 
@@ -634,15 +762,30 @@ int bmm_autotune_load(const char* path) {
   std::ifstream f(path);
   if (!f) return fail(BMM_E_INVAL, "cannot read %s", path);
   std::string line;
-  int loaded = 0;
   while (std::getline(f, line)) {
     if (line.empty() || line[0] == '#') continue;
-    int sr, leaf, tile;
-    long long m, k, n;
-    if (sscanf(line.c_str(), "%d %lld %lld %lld %d %d", &sr, &m, &k, &n, &leaf, &tile) != 6)
+    int sr, leaf, t1, t2, t3, d, ds;
+    long long m, k, n, b;
+    if (sscanf(line.c_str(), "leaf %d %lld %lld %lld %lld %d %d %d %d", &sr, &m, &k, &n, &b,
+               &leaf, &t1, &t2, &t3) == 9) {
+      int cnt = 0;
+      if ((sr != BMM_GF2 && sr != BMM_BOOLEAN) || m <= 0 || n <= 0 || k < 0 || b <= 0 ||
+          leaf < 1 || leaf > 3 || t1 < 0 || t1 > 1 || t2 < 0 || t3 < 0 ||
+          bmm_leaf_tiles(BMM_LEAF_MFMA_I8, &cnt) != BMM_OK || t2 > cnt || t3 > cnt)
+        return fail(BMM_E_INVAL, "bad leaf line: %s", line.c_str());
+      std::lock_guard<std::mutex> lock(g_mu);
+      TuneVal& v = g_tune[{sr, m, k, n, batch_bucket(b)}];
+      v.best_leaf = leaf;
+      v.tile[1] = t1;
+      v.tile[2] = t2;
+      v.tile[3] = t3;
+    } else if (sscanf(line.c_str(), "depth %lld %lld %lld %d %d", &m, &k, &n, &d, &ds) == 5) {
+      if (d < 0 || ds < 0 || ds > d) return fail(BMM_E_INVAL, "bad depth line: %s", line.c_str());
+      std::lock_guard<std::mutex> lock(g_mu);
+      g_depth[{m, k, n}] = {d, ds};
+    } else {
       return fail(BMM_E_INVAL, "bad line in %s: %s", path, line.c_str());
-    BMM_TRY(bmm_autotune_set(sr, m, k, n, leaf, tile));
-    ++loaded;
+    }
   }
   return BMM_OK;
 }
@@ -677,6 +820,7 @@ void bmm_finalize(void) {
   (void)hipSetDevice(cur);
   g_scratch.clear();
   g_tune.clear();
+  g_depth.clear();
 }
 
 }  // extern "C"

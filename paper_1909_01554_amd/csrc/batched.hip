@@ -18,9 +18,9 @@ __global__ void reset_counter(unsigned int* counter) {
 template <int KV>
 __device__ __forceinline__ void run_tile(const BatchedDesc& d, int64_t tm, int64_t tn) {
   if (d.semiring == GF2)
-    mfma::tile<GF2, 2, 2, KV>(d.A, d.lda, d.BT, d.ldbt, d.C, d.ldc, d.m, d.k, d.n, tm, tn, 0);
+    mfma::tile<GF2, 2, 2, KV, mfma::FMT_I8>(d.A, d.lda, d.BT, d.ldbt, d.C, d.ldc, d.m, d.k, d.n, tm, tn, 0);
   else
-    mfma::tile<BOOLEAN, 2, 2, KV>(d.A, d.lda, d.BT, d.ldbt, d.C, d.ldc, d.m, d.k, d.n, tm, tn,
+    mfma::tile<BOOLEAN, 2, 2, KV, mfma::FMT_I8>(d.A, d.lda, d.BT, d.ldbt, d.C, d.ldc, d.m, d.k, d.n, tm, tn,
                                   0);
 }
 

@@ -29,11 +29,44 @@ struct LeafBatch {
   int accumulate;
 };
 
+// XCD-aware order of workgroups over a batch of 2-D tile grids.  The hardware
+// hands workgroup g to XCD g % 8 (round robin); remapping g so that each XCD
+// owns one contiguous range of logical workgroups, walked in groups of
+// kGroupRows tile rows, keeps the operand panels of the tiles that run
+// together on one XCD inside that XCD's L2.  Any remapping is a bijection, so
+// correctness never depends on the dispatch order.
+constexpr int kXcds = 8;
+constexpr int kGroupRows = 8;
+
+struct TileCoord {
+  int64_t b, tm, tn;
+};
+
+__device__ __forceinline__ TileCoord xcd_tile(int64_t g, int64_t total, int64_t grid_m,
+                                              int64_t grid_n) {
+  const int64_t x = g % kXcds, j = g / kXcds;
+  const int64_t per = total / kXcds, rem = total % kXcds;
+  const int64_t t = x * per + (x < rem ? x : rem) + j;
+  const int64_t per_item = grid_m * grid_n;
+  TileCoord c;
+  c.b = t / per_item;
+  const int64_t r = t - c.b * per_item;
+  const int64_t band = (int64_t)kGroupRows * grid_n;
+  const int64_t first = (r / band) * kGroupRows;
+  const int64_t rows = grid_m - first < kGroupRows ? grid_m - first : kGroupRows;
+  const int64_t q = r - (r / band) * band;
+  c.tm = first + q % rows;
+  c.tn = q / rows;
+  return c;
+}
+
 // MFMA leaf variants (rows x cols of C per wave).
 enum MfmaTile { MFMA_128x64 = 0, MFMA_64x64 = 1, MFMA_64x128 = 2, MFMA_64x32 = 3,
                 MFMA_NUM_TILES };
 
 hipError_t launch_leaf_mfma(int semiring, const LeafBatch& p, int tile, hipStream_t s);
+// The same tiles on E2M1 (fp4) operands with exact fp32 sums; requires k < 2^24.
+hipError_t launch_leaf_mfma_f4(int semiring, const LeafBatch& p, int tile, hipStream_t s);
 hipError_t launch_leaf_valu(int semiring, const LeafBatch& p, int tile, hipStream_t s);
 int leaf_mfma_tile_rows(int tile);
 int leaf_mfma_tile_cols(int tile);

@@ -25,50 +25,48 @@
 namespace bmm {
 namespace {
 
-constexpr int kWaves = 4;
-
-template <int SEMI, int RA, int RB, int KV>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void leaf_mfma_kernel(LeafBatch p, int64_t tiles_m,
-                                                        int64_t tiles_n) {
-  const int64_t tile = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
-  const int64_t per = tiles_m * tiles_n;
-  const int64_t b = tile / per;
-  if (b >= p.batch) return;  // uniform per wave; no block-level barriers below
-  const int64_t t = tile - b * per;
-  const int64_t tm = t / tiles_n;
-  const int64_t tn = t - tm * tiles_n;
-  mfma::tile<SEMI, RA, RB, KV>(p.A + b * p.strideA, p.lda, p.BT + b * p.strideB, p.ldbt,
-                               p.C + b * p.strideC, p.ldc, p.m, p.k, p.n, tm, tn,
-                               p.accumulate);
+// Each workgroup owns 2 x 2 wave tiles; workgroups are ordered for L2 reuse per XCD.
+template <int SEMI, int RA, int RB, int KV, int FMT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void leaf_mfma_kernel(
+    LeafBatch p, int64_t tiles_m, int64_t tiles_n) {
+  const int64_t grid_m = (tiles_m + 1) >> 1, grid_n = (tiles_n + 1) >> 1;
+  const TileCoord c = xcd_tile(blockIdx.x, gridDim.x, grid_m, grid_n);
+  const int w = threadIdx.x >> 6;
+  const int64_t tm = 2 * c.tm + (w >> 1);
+  const int64_t tn = 2 * c.tn + (w & 1);
+  if (c.b >= p.batch || tm >= tiles_m || tn >= tiles_n) return;  // uniform per wave
+  const int64_t b = c.b;
+  mfma::tile<SEMI, RA, RB, KV, FMT>(p.A + b * p.strideA, p.lda, p.BT + b * p.strideB, p.ldbt,
+                                    p.C + b * p.strideC, p.ldc, p.m, p.k, p.n, tm, tn,
+                                    p.accumulate);
 }
 
-template <int SEMI, int RA, int RB>
+template <int SEMI, int RA, int RB, int FMT>
 hipError_t launch_t(const LeafBatch& p, hipStream_t s) {
   constexpr int TM = 32 * RA, TN = 32 * RB;
   const int64_t tiles_m = (p.m + TM - 1) / TM;
   // cover whole 64-bit output words, so padding dwords are written (as zero)
   const int64_t tiles_n = (((p.n + 63) / 64) * 64 + TN - 1) / TN;
-  const int64_t total = tiles_m * tiles_n * p.batch;
-  if (total == 0) return hipSuccess;
-  const int64_t blocks = (total + kWaves - 1) / kWaves;
+  const int64_t blocks = ((tiles_m + 1) / 2) * ((tiles_n + 1) / 2) * p.batch;
+  if (blocks == 0) return hipSuccess;
   const bool aligned16 = ((reinterpret_cast<uintptr_t>(p.A) | reinterpret_cast<uintptr_t>(p.BT)) & 15) == 0 &&
                          ((p.lda | p.ldbt | p.strideA | p.strideB) & 1) == 0;
   if (aligned16)
-    hipLaunchKernelGGL((leaf_mfma_kernel<SEMI, RA, RB, 2>), dim3((unsigned)blocks), dim3(256), 0, s,
+    hipLaunchKernelGGL((leaf_mfma_kernel<SEMI, RA, RB, 2, FMT>), dim3((unsigned)blocks), dim3(256), 0, s,
                        p, tiles_m, tiles_n);
   else
-    hipLaunchKernelGGL((leaf_mfma_kernel<SEMI, RA, RB, 1>), dim3((unsigned)blocks), dim3(256), 0, s,
+    hipLaunchKernelGGL((leaf_mfma_kernel<SEMI, RA, RB, 1, FMT>), dim3((unsigned)blocks), dim3(256), 0, s,
                        p, tiles_m, tiles_n);
   return hipGetLastError();
 }
 
-template <int SEMI>
+template <int SEMI, int FMT>
 hipError_t launch_semi(const LeafBatch& p, int tile, hipStream_t s) {
   switch (tile) {
-    case MFMA_64x64: return launch_t<SEMI, 2, 2>(p, s);
-    case MFMA_64x128: return launch_t<SEMI, 2, 4>(p, s);
-    case MFMA_64x32: return launch_t<SEMI, 2, 1>(p, s);
-    default: return launch_t<SEMI, 4, 2>(p, s);
+    case MFMA_64x64: return launch_t<SEMI, 2, 2, FMT>(p, s);
+    case MFMA_64x128: return launch_t<SEMI, 2, 4, FMT>(p, s);
+    case MFMA_64x32: return launch_t<SEMI, 2, 1, FMT>(p, s);
+    default: return launch_t<SEMI, 4, 2, FMT>(p, s);
   }
 }
 
@@ -94,7 +92,14 @@ int leaf_mfma_tile_cols(int tile) {
 
 hipError_t launch_leaf_mfma(int semiring, const LeafBatch& p, int tile, hipStream_t s) {
   if (p.m <= 0 || p.n <= 0 || p.batch <= 0) return hipSuccess;
-  return semiring == GF2 ? launch_semi<GF2>(p, tile, s) : launch_semi<BOOLEAN>(p, tile, s);
+  return semiring == GF2 ? launch_semi<GF2, mfma::FMT_I8>(p, tile, s)
+                         : launch_semi<BOOLEAN, mfma::FMT_I8>(p, tile, s);
+}
+
+hipError_t launch_leaf_mfma_f4(int semiring, const LeafBatch& p, int tile, hipStream_t s) {
+  if (p.m <= 0 || p.n <= 0 || p.batch <= 0) return hipSuccess;
+  return semiring == GF2 ? launch_semi<GF2, mfma::FMT_F4>(p, tile, s)
+                         : launch_semi<BOOLEAN, mfma::FMT_F4>(p, tile, s);
 }
 
 }  // namespace bmm

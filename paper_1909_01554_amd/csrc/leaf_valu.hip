@@ -41,12 +41,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void l
   const int wy = wave >> 1, wx = wave & 1;
   const int a = lane & 7, bb = lane >> 3;
 
-  const int64_t per = tiles_m * tiles_n;
-  const int64_t b = (int64_t)blockIdx.x / per;
+  // workgroups ordered for L2 reuse per XCD
+  const TileCoord c = xcd_tile(blockIdx.x, gridDim.x, tiles_m, tiles_n);
+  const int64_t b = c.b;
   if (b >= p.batch) return;  // uniform per workgroup
-  const int64_t t = (int64_t)blockIdx.x - b * per;
-  const int64_t tm = t / tiles_n;
-  const int64_t tn = t - tm * tiles_n;
+  const int64_t tm = c.tm;
+  const int64_t tn = c.tn;
   const uint64_t* A = p.A + b * p.strideA;
   const uint64_t* BT = p.BT + b * p.strideB;
   const int64_t kw = (p.k + 63) >> 6;

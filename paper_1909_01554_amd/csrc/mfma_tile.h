@@ -8,7 +8,36 @@ namespace bmm {
 namespace mfma {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v8i __attribute__((ext_vector_type(8)));
 typedef int v16i __attribute__((ext_vector_type(16)));
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+// Operand formats of the matrix cores.  I8: v_mfma_i32_32x32x32_i8, int32
+// counts.  F4: v_mfma_scale_f32_32x32x64_f8f6f4 on E2M1 operands with unit
+// scales; a set bit becomes the nibble 0x1 (the value 0.5), so every product
+// is 0.25 and the fp32 accumulator holds count / 4 exactly while k < 2^24.
+enum MfmaFormat { FMT_I8 = 0, FMT_F4 = 1 };
+
+template <int FMT>
+struct Acc;
+template <>
+struct Acc<FMT_I8> {
+  using type = v16i;
+};
+template <>
+struct Acc<FMT_F4> {
+  using type = v16f;
+};
+
+// Eight E2M1 operand nibbles per dword: nibble j of dword d is bit 4j + d of x.
+__device__ __forceinline__ v8i expand_f4(uint32_t x) {
+  v8i o;
+#pragma unroll
+  for (int d = 0; d < 4; ++d) o[d] = (int)((x >> d) & 0x11111111u);
+#pragma unroll
+  for (int d = 4; d < 8; ++d) o[d] = 0;
+  return o;
+}
 
 template <int SEMI>
 __device__ __forceinline__ v4i expand4(uint32_t x, int first) {
@@ -22,9 +51,27 @@ __device__ __forceinline__ v4i expand4(uint32_t x, int first) {
   return o;
 }
 
-template <int SEMI, int RA, int RB>
+template <int SEMI, int RA, int RB, int FMT>
 __device__ __forceinline__ void mfma_word(const uint64_t (&xa)[RA], const uint64_t (&xb)[RB],
-                                          v16i (&acc)[RA][RB]) {
+                                          typename Acc<FMT>::type (&acc)[RA][RB]) {
+  if constexpr (FMT == FMT_F4) {
+    // one MFMA per 32-bit half: 32 k values per lane, 64 per instruction
+#pragma unroll
+    for (int hw = 0; hw < 2; ++hw) {
+      v8i oa[RA], ob[RB];
+#pragma unroll
+      for (int f = 0; f < RA; ++f) oa[f] = expand_f4((uint32_t)(xa[f] >> (32 * hw)));
+#pragma unroll
+      for (int g = 0; g < RB; ++g) ob[g] = expand_f4((uint32_t)(xb[g] >> (32 * hw)));
+#pragma unroll
+      for (int f = 0; f < RA; ++f)
+#pragma unroll
+        for (int g = 0; g < RB; ++g)
+          acc[f][g] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+              oa[f], ob[g], acc[f][g], 4, 4, 0, 127, 0, 127);
+    }
+    return;
+  } else {
 #pragma unroll
   for (int hw = 0; hw < 2; ++hw) {
 #pragma unroll
@@ -41,11 +88,12 @@ __device__ __forceinline__ void mfma_word(const uint64_t (&xa)[RA], const uint64
           acc[f][g] = __builtin_amdgcn_mfma_i32_32x32x32_i8(oa[f], ob[g], acc[f][g], 0, 0, 0);
     }
   }
+  }
 }
 
 // KV = 64-bit words per lane per load (1: 8-byte loads, 2: 16-byte loads when
 // the operands are 16-byte aligned).  Lane half h takes words 2*KV*step + KV*h + v.
-template <int SEMI, int RA, int RB, int KV>
+template <int SEMI, int RA, int RB, int KV, int FMT>
 __device__ __forceinline__ void tile(const uint64_t* __restrict__ A, int64_t lda,
                                      const uint64_t* __restrict__ BT, int64_t ldbt,
                                      uint64_t* __restrict__ Cm, int64_t ldc, int64_t m,
@@ -72,16 +120,22 @@ __device__ __forceinline__ void tile(const uint64_t* __restrict__ A, int64_t lda
     brow[g] = BT + c * ldbt + KV * half;
   }
 
-  v16i acc[RA][RB];
+  using AccV = typename Acc<FMT>::type;
+  AccV acc[RA][RB];
 #pragma unroll
   for (int f = 0; f < RA; ++f)
 #pragma unroll
-    for (int g = 0; g < RB; ++g) acc[f][g] = v16i{};
+    for (int g = 0; g < RB; ++g) acc[f][g] = AccV{};
 
+  // Main loop over full steps of 2*KV words, software-pipelined: the words of
+  // step st+1 are requested before the MFMAs of step st are issued, so the
+  // memory latency hides behind a whole step of matrix-core work.
+  // Two register buffers alternate (the loop is unrolled by two), so no copy
+  // of a loaded buffer is ever needed inside the loop.
   const int64_t full_steps = kw / (2 * KV);
-  for (int64_t st = 0; st < full_steps; ++st) {
+  uint64_t a0[KV][RA], b0[KV][RB], a1[KV][RA], b1[KV][RB];
+  auto fetch = [&](int64_t st, uint64_t (&xa)[KV][RA], uint64_t (&xb)[KV][RB]) {
     const int64_t w = st * 2 * KV;
-    uint64_t xa[KV][RA], xb[KV][RB];
     if constexpr (KV == 2) {
 #pragma unroll
       for (int f = 0; f < RA; ++f) {
@@ -101,9 +155,23 @@ __device__ __forceinline__ void tile(const uint64_t* __restrict__ A, int64_t lda
 #pragma unroll
       for (int g = 0; g < RB; ++g) xb[0][g] = brow[g][w];
     }
+  };
+  auto compute = [&](const uint64_t (&xa)[KV][RA], const uint64_t (&xb)[KV][RB]) {
 #pragma unroll
-    for (int v = 0; v < KV; ++v) mfma_word<SEMI, RA, RB>(xa[v], xb[v], acc);
+    for (int v = 0; v < KV; ++v) mfma_word<SEMI, RA, RB, FMT>(xa[v], xb[v], acc);
+  };
+  if (full_steps > 0) fetch(0, a0, b0);
+  int64_t st = 0;
+  // sched_barrier(0) keeps the scheduler from sinking the loads below the MFMAs
+  for (; st + 1 < full_steps; st += 2) {
+    fetch(st + 1, a1, b1);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(a0, b0);
+    if (st + 2 < full_steps) fetch(st + 2, a0, b0);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(a1, b1);
   }
+  if (st < full_steps) compute(a0, b0);
   // Tail: words past the end of the row read as zero.
   {
     const int64_t w = full_steps * 2 * KV;
@@ -116,7 +184,7 @@ __device__ __forceinline__ void tile(const uint64_t* __restrict__ A, int64_t lda
         for (int f = 0; f < RA; ++f) xa[f] = wi < kw ? arow[f][w + v] : 0ull;
 #pragma unroll
         for (int g = 0; g < RB; ++g) xb[g] = wi < kw ? brow[g][w + v] : 0ull;
-        mfma_word<SEMI, RA, RB>(xa, xb, acc);
+        mfma_word<SEMI, RA, RB, FMT>(xa, xb, acc);
       }
     }
   }
@@ -139,7 +207,11 @@ __device__ __forceinline__ void tile(const uint64_t* __restrict__ A, int64_t lda
       uint32_t mine = 0;
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
-        const int cnt = acc[f][g][v];
+        int cnt;
+        if constexpr (FMT == FMT_F4)
+          cnt = __float2int_rn(acc[f][g][v] * 4.0f);  // exact: a multiple of 0.25
+        else
+          cnt = acc[f][g][v];
         const bool bit = (SEMI == GF2) ? ((cnt & 1) != 0) : (cnt != 0);
         const uint64_t bal = __ballot(bit);
         const uint32_t word = myhi ? (uint32_t)(bal >> 32) : (uint32_t)bal;

@@ -95,6 +95,9 @@ extern "C" int bmm_ooc(int semiring, const uint64_t* A, int64_t lda, const uint6
   const int64_t bkw = (bk + 63) / 64, bnw = bn / 64;
 
   int leaf = o.leaf == BMM_LEAF_AUTO ? BMM_LEAF_MFMA_I8 : o.leaf;
+  if (leaf < BMM_LEAF_VALU || leaf > BMM_LEAF_MFMA_F4) return ofail(BMM_E_INVAL, "unknown leaf");
+  if (leaf == BMM_LEAF_MFMA_F4 && std::min(block, k) >= ((int64_t)1 << 24))
+    return ofail(BMM_E_UNSUPPORTED, "the fp4 leaf counts exactly only for k < 2^24");
   int tile = o.tile > 0 ? o.tile : 1;
 
   const auto t0 = std::chrono::steady_clock::now();
@@ -152,8 +155,9 @@ extern "C" int bmm_ooc(int semiring, const uint64_t* A, int64_t lda, const uint6
                        "transpose"));
         LeafBatch p{R.a[s], bkw, 0, R.bt, bkw, 0, R.c[cs], bnw, 0, rows, depth, cols, 1,
                     J > 0 ? 1 : 0};
-        hipError_t e = leaf == BMM_LEAF_VALU ? launch_leaf_valu(semiring, p, tile - 1, R.comp)
-                                             : launch_leaf_mfma(semiring, p, tile - 1, R.comp);
+        hipError_t e = leaf == BMM_LEAF_VALU     ? launch_leaf_valu(semiring, p, tile - 1, R.comp)
+                       : leaf == BMM_LEAF_MFMA_F4 ? launch_leaf_mfma_f4(semiring, p, tile - 1, R.comp)
+                                                  : launch_leaf_mfma(semiring, p, tile - 1, R.comp);
         OOC_TRY(hip_ok(e, "leaf"));
         OOC_TRY(hip_ok(hipEventRecord(R.used[s], R.comp), "record"));
         ++step;

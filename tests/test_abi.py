@@ -91,6 +91,7 @@ def test_leaf_tiles_and_status_strings():
     import paper_1909_01554_amd as bmm
     assert bmm.bmm_leaf_tiles(bmm.LEAF_VALU) == 1
     assert bmm.bmm_leaf_tiles(bmm.LEAF_MFMA_I8) == 4
+    assert bmm.bmm_leaf_tiles(bmm.LEAF_MFMA_F4) == 4
     assert bmm.bmm_leaf_tile_shape(bmm.LEAF_MFMA_I8, 1) == (128, 64)
     assert bmm.bmm_leaf_tile_shape(bmm.LEAF_VALU, 1) == (128, 128)
     assert "gfx950" in bmm.bmm_version()
@@ -101,7 +102,7 @@ def test_autotune_table_roundtrip(tmp_path):
     bmm.bmm_autotune_set(bmm.GF2, 100, 200, 300, bmm.LEAF_VALU, 1)
     p = tmp_path / "tune.txt"
     bmm.bmm_autotune_save(str(p))
-    assert "0 100 200 300 1 1" in p.read_text()
+    assert "leaf 0 100 200 300 1 1 1 0 0" in p.read_text()
     bmm.bmm_autotune_load(str(p))
     with pytest.raises(bmm.BmmError):
         bmm.bmm_autotune_set(bmm.GF2, 1, 1, 1, bmm.LEAF_MFMA_I8, 9)
