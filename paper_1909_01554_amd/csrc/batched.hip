@@ -25,19 +25,29 @@ __device__ __forceinline__ void run_tile(const BatchedDesc& d, int64_t tm, int64
 }
 
 __global__ __launch_bounds__(256) void batched_kernel(const BatchedDesc* __restrict__ descs,
+                                                      const uint32_t* __restrict__ begins,
                                                       int64_t count, int64_t total_tiles,
-                                                      unsigned int* __restrict__ counter) {
+                                                      unsigned int* __restrict__ counter,
+                                                      int cached) {
+  // Each persistent workgroup copies the problems' first-tile indices into LDS
+  // once (when they fit), so finding a tile's problem is an LDS binary search.
+  extern __shared__ uint32_t sbeg[];
+  if (cached) {
+    for (int64_t i = threadIdx.x; i < count; i += blockDim.x) sbeg[i] = begins[i];
+    __syncthreads();
+  }
   const int lane = threadIdx.x & 63;
   while (true) {
     unsigned int t = 0;
     if (lane == 0) t = atomicAdd(counter, 1u);
     t = __shfl(t, 0);
     if ((int64_t)t >= total_tiles) break;  // every wave exits once the queue is drained
-    // binary search: last problem with tile_begin <= t
+    // binary search: last problem whose first tile is <= t
     int64_t lo = 0, hi = count - 1;
     while (lo < hi) {
       const int64_t mid = (lo + hi + 1) >> 1;
-      if (descs[mid].tile_begin <= (int64_t)t) lo = mid;
+      const uint32_t b = cached ? sbeg[mid] : begins[mid];
+      if (b <= t) lo = mid;
       else hi = mid - 1;
     }
     const BatchedDesc d = descs[lo];
@@ -56,15 +66,17 @@ __global__ __launch_bounds__(256) void batched_kernel(const BatchedDesc* __restr
 int batched_tile_rows() { return 64; }
 int batched_tile_cols() { return 64; }
 
-hipError_t launch_batched_persistent(const BatchedDesc* descs, int64_t count,
-                                     int64_t total_tiles, unsigned int* counter, int grid,
-                                     hipStream_t s) {
+hipError_t launch_batched_persistent(const BatchedDesc* descs, const uint32_t* begins,
+                                     int64_t count, int64_t total_tiles, unsigned int* counter,
+                                     int grid, hipStream_t s) {
   if (count <= 0 || total_tiles <= 0) return hipSuccess;
   hipLaunchKernelGGL(reset_counter, dim3(1), dim3(64), 0, s, counter);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(batched_kernel, dim3((unsigned)grid), dim3(256), 0, s, descs, count,
-                     total_tiles, counter);
+  const int cached = count <= kBatchedLdsProblems ? 1 : 0;
+  const size_t lds = cached ? (size_t)count * sizeof(uint32_t) : 0;
+  hipLaunchKernelGGL(batched_kernel, dim3((unsigned)grid), dim3(256), lds, s, descs, begins,
+                     count, total_tiles, counter, cached);
   return hipGetLastError();
 }
 

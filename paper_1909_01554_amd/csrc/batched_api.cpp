@@ -19,6 +19,7 @@ namespace {
 
 struct Plan {
   BatchedDesc* descs = nullptr;  // device
+  uint32_t* begins = nullptr;    // device: first tile of each problem
   unsigned int* counter = nullptr;
   int64_t count = 0;
   int64_t total_tiles = 0;
@@ -78,24 +79,33 @@ int build_plan(const bmm_problem* problems, int64_t count, Plan* out) {
     tiles += ((p.m + TR - 1) / TR) * d.tiles_n;
     host.push_back(d);
   }
+  if (tiles >= ((int64_t)1 << 32) - ((int64_t)1 << 20))
+    return bfail(BMM_E_UNSUPPORTED, "batched plans hold fewer than 2^32 tiles (%ld)", (long)tiles);
   Plan P;
   P.count = (int64_t)host.size();
   P.total_tiles = tiles;
+  std::vector<uint32_t> begins;
+  for (const auto& d : host) begins.push_back((uint32_t)d.tile_begin);
   if (hipGetDevice(&P.device) != hipSuccess) return bfail(BMM_E_DEVICE, "hipGetDevice");
   int cus = 256;
   hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, P.device);
   P.grid = std::max(1, cus * 4);
   if (P.count > 0) {
     if (hipMalloc((void**)&P.descs, sizeof(BatchedDesc) * host.size()) != hipSuccess ||
+        hipMalloc((void**)&P.begins, sizeof(uint32_t) * begins.size()) != hipSuccess ||
         hipMalloc((void**)&P.counter, 256) != hipSuccess) {
       (void)hipGetLastError();
-      hipFree(P.descs);
+      (void)hipFree(P.descs);
+      (void)hipFree(P.begins);
       return bfail(BMM_E_NOMEM, "plan allocation");
     }
     if (hipMemcpy(P.descs, host.data(), sizeof(BatchedDesc) * host.size(),
+                  hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(P.begins, begins.data(), sizeof(uint32_t) * begins.size(),
                   hipMemcpyHostToDevice) != hipSuccess) {
-      hipFree(P.descs);
-      hipFree(P.counter);
+      (void)hipFree(P.descs);
+      (void)hipFree(P.begins);
+      (void)hipFree(P.counter);
       return bfail(BMM_E_DEVICE, "plan upload: %s", hipGetErrorString(hipGetLastError()));
     }
   }
@@ -123,8 +133,8 @@ int bmm_batched_plan_create(const bmm_problem* problems, int64_t count,
 int bmm_batched_plan_launch(void* plan, void* hip_stream) {
   if (!plan) return bfail(BMM_E_INVAL, "null plan");
   Plan* P = static_cast<Plan*>(plan);
-  hipError_t e = launch_batched_persistent(P->descs, P->count, P->total_tiles, P->counter,
-                                           P->grid, (hipStream_t)hip_stream);
+  hipError_t e = launch_batched_persistent(P->descs, P->begins, P->count, P->total_tiles,
+                                           P->counter, P->grid, (hipStream_t)hip_stream);
   if (e != hipSuccess) return bfail(BMM_E_DEVICE, "batched launch: %s", hipGetErrorString(e));
   return BMM_OK;
 }
@@ -138,6 +148,7 @@ void bmm_batched_plan_destroy(void* plan) {
     (void)hipSetDevice(P->device);
     (void)hipDeviceSynchronize();
     (void)hipFree(P->descs);
+    (void)hipFree(P->begins);
     (void)hipFree(P->counter);
     (void)hipSetDevice(cur);
   }

@@ -91,6 +91,54 @@ __device__ __forceinline__ void mfma_word(const uint64_t (&xa)[RA], const uint64
   }
 }
 
+// Epilogue of a TM x TN wave tile (TM = 32*RA, TN = 32*RB) at tile coordinates
+// (tm, tn): reduce counts to bits and pack 32 columns per dword with ballots.
+template <int SEMI, int RA, int RB, int FMT>
+__device__ __forceinline__ void epilogue(const typename Acc<FMT>::type (&acc)[RA][RB],
+                                         uint64_t* __restrict__ Cm, int64_t ldc, int64_t m,
+                                         int64_t n, int64_t tm, int64_t tn, int accumulate) {
+  constexpr int TM = 32 * RA, TN = 32 * RB;
+  const int lane = threadIdx.x & 63;
+  const int half = lane >> 5;
+  const int li = lane & 31;
+  uint32_t* C32 = reinterpret_cast<uint32_t*>(Cm);
+  const int64_t ldc32 = 2 * ldc;
+  const int64_t n_words32 = ((n + 63) >> 6) * 2;  // dwords per C row incl. padding
+  const int myv = ((li >> 3) << 2) | (li & 3);
+  const int myhi = (li >> 2) & 1;
+#pragma unroll
+  for (int g = 0; g < RB; ++g) {
+    const int64_t c0 = tn * TN + 32 * g;
+    const int64_t cw = c0 >> 5;
+    if (cw >= n_words32) continue;  // uniform
+    const int64_t valid = n - c0;
+    const uint32_t cmask = valid >= 32 ? 0xFFFFFFFFu : (valid > 0 ? ((1u << valid) - 1u) : 0u);
+#pragma unroll
+    for (int f = 0; f < RA; ++f) {
+      uint32_t mine = 0;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        int cnt;
+        if constexpr (FMT == FMT_F4)
+          cnt = __float2int_rn(acc[f][g][v] * 4.0f);  // exact: a multiple of 0.25
+        else
+          cnt = acc[f][g][v];
+        const bool bit = (SEMI == GF2) ? ((cnt & 1) != 0) : (cnt != 0);
+        const uint64_t bal = __ballot(bit);
+        const uint32_t word = myhi ? (uint32_t)(bal >> 32) : (uint32_t)bal;
+        mine = (myv == v) ? word : mine;
+      }
+      mine &= cmask;
+      const int64_t row = tm * TM + 32 * f + li;
+      if (half == 0 && row < m) {
+        uint32_t* dst = C32 + row * ldc32 + cw;
+        if (accumulate) mine = (SEMI == GF2) ? (mine ^ *dst) : (mine | *dst);
+        *dst = mine;
+      }
+    }
+  }
+}
+
 // KV = 64-bit words per lane per load (1: 8-byte loads, 2: 16-byte loads when
 // the operands are 16-byte aligned).  Lane half h takes words 2*KV*step + KV*h + v.
 template <int SEMI, int RA, int RB, int KV, int FMT>
@@ -189,43 +237,7 @@ __device__ __forceinline__ void tile(const uint64_t* __restrict__ A, int64_t lda
     }
   }
 
-  // Epilogue: reduce counts to bits and pack 32 columns per dword with ballots.
-  uint32_t* C32 = reinterpret_cast<uint32_t*>(Cm);
-  const int64_t ldc32 = 2 * ldc;
-  const int64_t n_words32 = ((n + 63) >> 6) * 2;  // dwords per C row incl. padding
-  const int myv = ((li >> 3) << 2) | (li & 3);
-  const int myhi = (li >> 2) & 1;
-#pragma unroll
-  for (int g = 0; g < RB; ++g) {
-    const int64_t c0 = tn * TN + 32 * g;
-    const int64_t cw = c0 >> 5;
-    if (cw >= n_words32) continue;  // uniform
-    const int64_t valid = n - c0;
-    const uint32_t cmask = valid >= 32 ? 0xFFFFFFFFu : (valid > 0 ? ((1u << valid) - 1u) : 0u);
-#pragma unroll
-    for (int f = 0; f < RA; ++f) {
-      uint32_t mine = 0;
-#pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        int cnt;
-        if constexpr (FMT == FMT_F4)
-          cnt = __float2int_rn(acc[f][g][v] * 4.0f);  // exact: a multiple of 0.25
-        else
-          cnt = acc[f][g][v];
-        const bool bit = (SEMI == GF2) ? ((cnt & 1) != 0) : (cnt != 0);
-        const uint64_t bal = __ballot(bit);
-        const uint32_t word = myhi ? (uint32_t)(bal >> 32) : (uint32_t)bal;
-        mine = (myv == v) ? word : mine;
-      }
-      mine &= cmask;
-      const int64_t row = tm * TM + 32 * f + li;
-      if (half == 0 && row < m) {
-        uint32_t* dst = C32 + row * ldc32 + cw;
-        if (accumulate) mine = (SEMI == GF2) ? (mine ^ *dst) : (mine | *dst);
-        *dst = mine;
-      }
-    }
-  }
+  epilogue<SEMI, RA, RB, FMT>(acc, Cm, ldc, m, n, tm, tn, accumulate);
 }
 
 }  // namespace mfma
