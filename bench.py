@@ -49,6 +49,9 @@ def parse():
     ap.add_argument("--leaf", choices=["mfma", "valu", "f4"], default="mfma",
                     help="leaf of the timed steps (mfma = int8 MFMA, f4 = E2M1 MFMA)")
     ap.add_argument("--no-f4", action="store_true", help="skip the fp4-leaf side step")
+    ap.add_argument("--no-schemes", action="store_true",
+                    help="skip timing the GF(2) recursion with the chaining and "
+                         "Strassen-Winograd schemes")
     ap.add_argument("--mode", choices=["step", "leaf", "batched", "ooc", "tune"], default="step",
                     help="leaf: one Boolean leaf launch plus a copy of known size (for "
                          "profiler counters); batched: 4096 uneven products in one "
@@ -66,25 +69,20 @@ def run_batched(args, torch, np, bmm, bmmgen):
     import oracle
     dev = torch.device("cuda:0")
     seed = bmmgen.config_seed(3)
-    rng = np.random.default_rng(seed)
-    shapes = np.exp(rng.uniform(np.log(256), np.log(8192), size=(args.problems, 3)))
-    shapes = np.clip((shapes // 64).astype(np.int64) * 64, 256, 8192)
+    shapes = bmmgen.batched_shapes(args.problems, seed)
     words = lambda x: (int(x) + 63) // 64
-    na = sum(int(m) * words(k) for m, k, n in shapes)
-    nb = sum(int(n) * words(k) for m, k, n in shapes)
-    nc = sum(int(m) * words(n) for m, k, n in shapes)
+    na = sum(m * words(k) for _, m, k, n, _ in shapes)
+    nb = sum(n * words(k) for _, m, k, n, _ in shapes)
+    nc = sum(m * words(n) for _, m, k, n, _ in shapes)
     log(f"[bench] batched: {args.problems} problems, operands "
         f"{(na + nb + nc) * 8 / 2**30:.2f} GiB")
     bufA = torch.empty(na, dtype=torch.int64, device=dev)
     bufB = torch.empty(nb, dtype=torch.int64, device=dev)
     bufC = torch.empty(nc, dtype=torch.int64, device=dev)
-    tmpB = torch.empty(max(int(k) * words(n) for m, k, n in shapes), dtype=torch.int64,
+    tmpB = torch.empty(max(k * words(n) for _, m, k, n, _ in shapes), dtype=torch.int64,
                        device=dev)
     probs, oa, ob, oc = [], 0, 0, 0
-    for p, (m, k, n) in enumerate(shapes):
-        m, k, n = int(m), int(k), int(n)
-        sr = bmm.GF2 if p % 2 == 0 else bmm.BOOLEAN
-        dist = bmmgen.Dist.half() if sr == bmm.GF2 else bmmgen.Dist.inv_sqrt(k)
+    for p, (sr, m, k, n, dist) in enumerate(shapes):
         A = bufA[oa:oa + m * words(k)].view(m, words(k))
         BT = bufB[ob:ob + n * words(k)].view(n, words(k))
         C = bufC[oc:oc + m * words(n)].view(m, words(n))
@@ -96,7 +94,22 @@ def run_batched(args, torch, np, bmm, bmmgen):
         probs.append(dict(semiring=sr, m=m, k=k, n=n, A=A, B=BT, C=C, b_transposed=True))
     torch.cuda.synchronize()
     bops = sum(2.0 * p["m"] * p["k"] * p["n"] for p in probs)
-    plan = bmm.BatchedPlan(probs)
+    # every (leaf, tile) candidate timed once for the record, then the autotuner's choice
+    cands = {}
+    for lf, lname in [(bmm.LEAF_MFMA_I8, "int8"), (bmm.LEAF_MFMA_F4, "fp4")]:
+        for tl, tname in [(1, "128x64"), (2, "64x64")]:
+            pl = bmm.BatchedPlan(probs, options=bmm.Options(leaf=lf, tile=tl))
+            pl.launch()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            pl.launch()
+            e1.record()
+            torch.cuda.synchronize()
+            cands[f"{lname}_{tname}"] = round(e0.elapsed_time(e1) / 1e3, 5)
+            pl.destroy()
+    leaf, tile, _ = bmm.bmm_autotune_batched(probs)
+    log(f"[bench] batched candidates {cands}; autotuner: leaf {leaf} tile {tile}")
+    plan = bmm.BatchedPlan(probs)  # AUTO options: the autotuner's choice
     s = torch.cuda.Stream()
     g = torch.cuda.CUDAGraph()
     with torch.cuda.stream(s):
@@ -113,7 +126,11 @@ def run_batched(args, torch, np, bmm, bmmgen):
         g.replay()
     torch.cuda.synchronize()
     t_graph = (time.perf_counter() - t0) / args.steps
-    opts = bmm.Options(leaf=bmm.LEAF_MFMA_I8, tile=2)
+    # rows of 16 problems from the graph replays, checked against the oracle below
+    check = list(range(0, args.problems, max(1, args.problems // 16)))
+    sample = {p: bmmgen.stratified_rows(probs[p]["m"], 8, seed + p) for p in check}
+    kept = {p: probs[p]["C"][sample[p]].cpu().numpy().view(np.uint64).copy() for p in check}
+    opts = bmm.Options(leaf=leaf)  # the baseline: the same leaf kind, tile chosen per product
 
     def one_by_one():
         for p in probs:
@@ -126,25 +143,29 @@ def run_batched(args, torch, np, bmm, bmmgen):
         one_by_one()
     torch.cuda.synchronize()
     t_loop = (time.perf_counter() - t0) / args.steps
-    # verify 16 problems on 8 stratified rows each against the oracle
+    # both variants' rows of the 16 problems against the oracle
     ok = True
-    for p in range(0, args.problems, max(1, args.problems // 16)):
+    for p in check:
         pr = probs[p]
         m, k, n = pr["m"], pr["k"], pr["n"]
         dist = bmmgen.Dist.half() if pr["semiring"] == bmm.GF2 else bmmgen.Dist.inv_sqrt(k)
-        rows = bmmgen.stratified_rows(m, 8, seed + p)
+        rows = sample[p]
         Ar = bmmgen.fill_rows_cpu(rows, k, seed, bmmgen.batched_tag(p, "A"), dist)
         Bh = bmmgen.fill_cpu(k, n, seed, bmmgen.batched_tag(p, "B"), dist)
         want = oracle.rows(Ar, Bh, k, n, pr["semiring"])
         got = pr["C"][rows].cpu().numpy().view(np.uint64)
-        ok = ok and bool(np.array_equal(got, want))
+        ok = ok and bool(np.array_equal(got, want)) and bool(np.array_equal(kept[p], want))
     plan.destroy()
     print(json.dumps({
         "mode": "batched", "problems": args.problems, "total_bops": bops,
         "persistent_graph_s": round(t_graph, 5), "persistent_pbops": round(bops / t_graph / 1e15, 4),
         "one_launch_per_product_s": round(t_loop, 5),
         "one_launch_per_product_pbops": round(bops / t_loop / 1e15, 4),
-        "speedup": round(t_loop / t_graph, 3), "verified_16_problems": ok}), flush=True)
+        "speedup": round(t_loop / t_graph, 3), "verified_16_problems": ok,
+        "autotuned": {"leaf": {2: "int8", 3: "fp4"}[leaf], "tile": {1: "128x64", 2: "64x64"}[tile]},
+        "candidates_s": cands,
+        "frac_of_peak": round(bops / t_graph / 1e12 / (PEAK_MFMA_F4_TOPS if leaf == 3
+                                                        else PEAK_MFMA_I8_TOPS), 4)}), flush=True)
 
 
 def run_ooc(args, torch, np, bmm, bmmgen):
@@ -273,14 +294,31 @@ def main():
     ws = torch.empty(nbytes // 8 + 1, dtype=torch.int64, device=dev)
     if args.mode == "tune":
         out = {"mode": "tune", "n": n}
-        # leaf table: the Boolean cubic shape (timed on a 16384-row proxy with the full k)
-        # and the Strassen leaf shapes of the admissible depths (batches of 64)
-        proxy = min(n, 16384)
-        for sr, name in [(bmm.BOOLEAN, "boolean"), (bmm.GF2, "gf2")]:
-            leaf, tile, secs = bmm.bmm_autotune_leaf(sr, proxy, n, proxy, 1)
-            bmm.bmm_autotune_set(sr, n, n, n, leaf, tile, batch=1)
-            out[f"cubic_{name}"] = {"leaf": leaf, "tile": tile, "proxy_s": secs}
-            log(f"[bench] tuned cubic {name} leaf={leaf} tile={tile}")
+        # leaf table: the full-size cubic shapes, one timed launch per (leaf, tile) on the
+        # step's own buffers (the dense leaves take the same time on any bits), and the
+        # Strassen leaf shapes of the admissible depths
+        for sr, name, A_, BT_, C_ in [(bmm.BOOLEAN, "boolean", Ab, BTb, Cb),
+                                      (bmm.GF2, "gf2", Ab, BTb, Cb)]:
+            bmm.bmm_transpose(Bb, BTb, n, n)
+            fn = bmm.bmm_boolean if sr == bmm.BOOLEAN else bmm.bmm_gf2
+            best = {}
+            for lf in (bmm.LEAF_VALU, bmm.LEAF_MFMA_I8, bmm.LEAF_MFMA_F4):
+                for t in range(1, bmm.bmm_leaf_tiles(lf) + 1):
+                    e = events()
+                    e[0].record(stream)
+                    fn(A_, BT_, C_, n, n, n, options=bmm.Options(leaf=lf, tile=t),
+                       b_transposed=True)
+                    e[1].record(stream)
+                    torch.cuda.synchronize()
+                    secs = e[0].elapsed_time(e[1]) / 1e3
+                    log(f"[bench] cubic {name} leaf={lf} tile={t}: {secs:.3f} s")
+                    if secs < best.get(lf, (1e30, 0))[0]:
+                        best[lf] = (secs, t)
+            order = sorted(best, key=lambda lf: -best[lf][0])  # fastest leaf set last
+            for lf in order:
+                bmm.bmm_autotune_set(sr, n, n, n, lf, best[lf][1])
+            out[f"cubic_{name}"] = {str(lf): {"tile": best[lf][1], "s": round(best[lf][0], 4)}
+                                    for lf in best}
         for d in range(4, 9):
             s_ = n >> d
             if s_ < 1024:
@@ -320,6 +358,15 @@ def main():
         step(LEAF[args.leaf])
         torch.cuda.synchronize()
 
+    # output rows kept from every variant below, checked against the oracle at the end
+    rows_sample = bmmgen.stratified_rows(n, max(2, args.cpu_rows), seed)
+    idx = torch.tensor(rows_sample, device=dev)
+    kept = {}
+
+    def keep(name, with_boolean=True):
+        kept[name] = (Cg.index_select(0, idx).cpu(),
+                      Cb.index_select(0, idx).cpu() if with_boolean else None)
+
     evs = [events() for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -327,6 +374,7 @@ def main():
         step(LEAF[args.leaf], evs[i])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    keep(args.leaf)
     step_s = (t1 - t0) / args.steps
     gf2_s = sum(e[0].elapsed_time(e[1]) for e in evs) / args.steps / 1e3
     tr_s = sum(e[1].elapsed_time(e[2]) for e in evs) / args.steps / 1e3
@@ -343,6 +391,7 @@ def main():
         vg = e[0].elapsed_time(e[1]) / 1e3
         vb = e[2].elapsed_time(e[3]) / 1e3
         vt = e[0].elapsed_time(e[3]) / 1e3
+        keep(name)
         log(f"[bench] {name} step {vt:.3f} s (GF(2) {vg:.3f} s, Boolean {vb:.3f} s)")
         return {"step_s": round(vt, 4), "value": round(2 * bops / vt / 1e15, 4),
                 "gf2_strassen_s": round(vg, 4), "gf2_eff_pbops": round(bops / vg / 1e15, 4),
@@ -356,10 +405,27 @@ def main():
     if not args.no_f4 and args.leaf != "f4":
         f4 = side_step("f4", PEAK_MFMA_F4_TOPS)
 
+    # the same GF(2) recursion (same depth and leaf) with the other 2 x 2 schemes
+    schemes = None
+    if not args.no_schemes:
+        schemes = {}
+        for name, sch in [("chaining", bmm.SCHEME_CHAINING),
+                          ("strassen_winograd", bmm.SCHEME_WINOGRAD)]:
+            o = opts(LEAF[args.leaf])
+            o.scheme = sch
+            e = events()
+            e[0].record(stream)
+            bmm.bmm_gf2_strassen(Ag, Bg, Cg, n, n, n, ws, depth=args.depth, options=o)
+            e[1].record(stream)
+            torch.cuda.synchronize()
+            t = e[0].elapsed_time(e[1]) / 1e3
+            keep(name, with_boolean=False)
+            schemes[name] = {"gf2_s": round(t, 4), "gf2_eff_pbops": round(bops / t / 1e15, 4)}
+            log(f"[bench] GF(2) {name} scheme {t:.3f} s")
+
     # Rows of both products, checked against the oracle; the GF(2) rows time the oracle.
     cpu = None
     verified = None
-    rows_sample = bmmgen.stratified_rows(n, max(2, args.cpu_rows), seed)
     if not args.no_cpu_baseline:
         import numpy as np
         import oracle
@@ -370,17 +436,18 @@ def main():
         c0 = time.perf_counter()
         want = oracle.rows(Ar, Bh, n, n, oracle.GF2)
         c1 = time.perf_counter()
-        idx = torch.tensor(rows_sample, device=dev)
-        got = Cg.index_select(0, idx).cpu().numpy().view(np.uint64)
-        ok_g = bool(np.array_equal(got, want))
         del Bh
         Bbh = bmmgen.fill_cpu(n, n, seed, 0x1B, bool_dist)
         Abr = bmmgen.fill_rows_cpu(rows_sample, n, seed, 0x1A, bool_dist)
         want_b = oracle.rows(Abr, Bbh, n, n, oracle.BOOLEAN)
-        got_b = Cb.index_select(0, idx).cpu().numpy().view(np.uint64)
-        ok_b = bool(np.array_equal(got_b, want_b))
         del Bbh
-        verified = {"rows": len(rows_sample), "gf2": ok_g, "boolean": ok_b}
+        # every variant's kept rows: the GF(2) product and (for leaf variants) the Boolean one
+        verified = {"rows": len(rows_sample)}
+        for name, (g, b) in kept.items():
+            verified[name] = {"gf2": bool(np.array_equal(g.numpy().view(np.uint64), want))}
+            if b is not None:
+                verified[name]["boolean"] = bool(
+                    np.array_equal(b.numpy().view(np.uint64), want_b))
         rate = 2.0 * len(rows_sample) * n * n / (c1 - c0)
         cpu = {"value": round(rate / 1e15, 8), "unit": "Pbop/s", "cores": threads,
                "kind": "oracle",
@@ -416,6 +483,7 @@ def main():
         },
         "valu_leaf": valu,
         "f4_leaf": f4,
+        "gf2_schemes": schemes,
         "roofline": {"bound": "alu" if args.leaf == "valu" else "mfma",
                      "kernel": ("leaf_valu_kernel" if args.leaf == "valu" else "leaf_mfma_kernel")
                                + " (Boolean cubic product, one launch per step)",

@@ -186,3 +186,29 @@ def stratified_rows(m, count, seed):
     if rows[-1] != m - 1:
         rows.append(m - 1)
     return sorted(set(rows))
+
+
+def freivalds_vectors(length, count, seed):
+    """`count` seeded Bernoulli(1/2) bit vectors of `length` bits (one packed row
+    each), vector v drawn under the tag 0xF0000 + v."""
+    out = np.zeros((count, words(length)), dtype=np.uint64)
+    for v in range(count):
+        out[v:v + 1] = fill_cpu(1, length, seed, freivalds_tag(v), Dist.half())
+    return out
+
+
+def batched_shapes(count, seed, lo=256, hi=8192, step=64):
+    """Shapes (m, k, n) of a batch of `count` independent products: each size
+    drawn log-uniform on [lo, hi] from numpy's PCG64 seeded with `seed`, floored
+    to a multiple of `step` and clamped to [lo, hi].  Problem p is over GF(2)
+    with Bernoulli(1/2) bits when p is even and Boolean with Bernoulli(1/sqrt(k))
+    bits when p is odd (semiring codes 0 and 1)."""
+    rng = np.random.default_rng(seed)
+    shapes = np.exp(rng.uniform(np.log(lo), np.log(hi), size=(count, 3)))
+    shapes = np.clip((shapes // step).astype(np.int64) * step, lo, hi)
+    out = []
+    for p, (m, k, n) in enumerate(shapes):
+        sr = 0 if p % 2 == 0 else 1
+        dist = Dist.half() if sr == 0 else Dist.inv_sqrt(int(k))
+        out.append((sr, int(m), int(k), int(n), dist))
+    return out

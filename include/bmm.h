@@ -63,6 +63,17 @@ typedef enum {
                            else BMM_E_UNSUPPORTED */
 } bmm_leaf;
 
+/* 2 x 2 schemes of the GF(2) recursion (bmm_options.scheme). */
+typedef enum {
+  BMM_SCHEME_SELF_INVERSE = 0, /* alternative basis, Theorem 1 (section 2.2): self-inverse,
+                                  in-place basis changes */
+  BMM_SCHEME_CHAINING = 1,     /* alternative basis, Theorem 2 (section 2.3): forward and
+                                  inverse changes are mutual inverses, so alternative-basis
+                                  products chain without changing back in between */
+  BMM_SCHEME_WINOGRAD = 2      /* Strassen-Winograd in the standard basis (section 2.1):
+                                  no basis changes */
+} bmm_scheme;
+
 /* Flags. */
 #define BMM_FLAG_ACCUMULATE 0x1u    /* C ^= AB (GF(2)) or C |= AB (Boolean) */
 #define BMM_FLAG_B_TRANSPOSED 0x2u  /* B is passed as B^T: n rows of k bits, pitch ldb */
@@ -79,6 +90,7 @@ typedef struct {
   int depth_parallel; /* Strassen levels processed breadth-first; -1 = auto */
   int64_t block;      /* out-of-core block size in bits (multiple of 64); 0 = auto */
   uint32_t flags;     /* BMM_FLAG_* */
+  int scheme;         /* bmm_scheme of the GF(2) recursion; 0 = self-inverse */
 } bmm_options;
 
 /* Fill *opt with the defaults (everything automatic, no flags). */
@@ -102,14 +114,20 @@ int bmm_boolean(const uint64_t* A, int64_t lda, const uint64_t* B, int64_t ldb, 
                 int64_t ldc, int64_t m, int64_t k, int64_t n, const bmm_options* opt,
                 void* hip_stream);
 
-/* GF(2) product by the self-inverse alternative-basis recursion with `depth`
- * levels of 2 x 2 blocks above a cubic leaf (depth -1 = autotuned; 0 = cubic).
+/* GF(2) product by the 2 x 2 recursion of opt->scheme (default: the
+ * self-inverse alternative basis, section 2.2; also the chaining alternative
+ * basis, section 2.3, and standard-basis Strassen-Winograd, section 2.1) with
+ * `depth` levels of 2 x 2 blocks above a cubic leaf (depth -1 = autotuned;
+ * 0 = cubic).
  * Requires m % 2^depth == 0, k % (64 * 2^depth) == 0 and n % (64 * 2^depth) == 0,
  * else BMM_E_UNSUPPORTED.  The workspace (device memory, >= the size from
  * bmm_gf2_strassen_workspace for the same arguments) holds the basis-changed
  * operands and the expanded levels; its contents on return are unspecified.
  * With BMM_FLAG_ALT_BASIS_IO the inputs are taken as A-hat, B-hat and C-hat is
- * returned (no basis changes).  Errors: as bmm_gf2, plus BMM_E_WORKSPACE. */
+ * returned (no basis changes).  With BMM_FLAG_ACCUMULATE the product is XORed
+ * into C (into C-hat under BMM_FLAG_ALT_BASIS_IO; otherwise C is taken to the
+ * alternative basis and back).
+ * Errors: as bmm_gf2, plus BMM_E_WORKSPACE. */
 int bmm_gf2_strassen(const uint64_t* A, int64_t lda, const uint64_t* B, int64_t ldb,
                      uint64_t* C, int64_t ldc, int64_t m, int64_t k, int64_t n, int depth,
                      void* workspace, size_t workspace_bytes, const bmm_options* opt,
@@ -147,14 +165,32 @@ int bmm_batched_plan_create(const bmm_problem* problems, int64_t count,
                             const bmm_options* opt, void** plan_out);
 int bmm_batched_plan_launch(void* plan, void* hip_stream);
 void bmm_batched_plan_destroy(void* plan);
+/* Leaf and tile of a batched plan: opt->leaf BMM_LEAF_MFMA_I8 or BMM_LEAF_MFMA_F4
+ * (BMM_LEAF_VALU: BMM_E_UNSUPPORTED), opt->tile 1 (128 x 64 output tile per wave)
+ * or 2 (64 x 64); 0 / AUTO take the autotuner's record for plans of the same
+ * problem count and total work (to a factor of two), else int8 with 64 x 64. */
+
+/* Autotuner for batched plans (the paper's empirical parameter choice,
+ * section 3.17, applied to the persistent launch): times one launch of the plan
+ * for every (leaf, tile) candidate on the default stream, records the fastest
+ * for later plans with AUTO options (saved by bmm_autotune_save), and returns
+ * it.  Problems as for bmm_batched_plan_create; their outputs are overwritten.
+ * Synchronous; allocates (plans). */
+int bmm_autotune_batched(const bmm_problem* problems, int64_t count, int* leaf_out,
+                         int* tile_out, double* seconds_out);
 
 /* Out-of-core product of page-locked host matrices (sections 3.3, 3.16, 3.18):
  * C = AB over `semiring` with A, B, C in host memory allocated by hipHostMalloc
  * (else BMM_E_INVAL).  b x b blocks (block bits, a multiple of 64; 0 = option
  * or 2^17) stream through two HBM slots with asynchronous copies on their own
  * streams, overlapped with the leaf; finished C blocks download while the next
- * block computes.  Synchronous: returns after C is complete; *seconds_out (if
- * not NULL) receives the wall time.  Allocates and frees its HBM buffers. */
+ * block computes.  Over GF(2) every block product whose shape admits at least
+ * one level runs the alternative-basis recursion in HBM: the uploaded blocks
+ * are basis-changed on the device, the products of one C block accumulate in
+ * the alternative basis, and the C block changes back once before download
+ * (depth_serial = depth_parallel = 0 in opt forces the cubic leaf).
+ * Synchronous: returns after C is complete; *seconds_out (if not NULL)
+ * receives the wall time.  Allocates and frees its HBM buffers. */
 int bmm_ooc(int semiring, const uint64_t* A, int64_t lda, const uint64_t* B, int64_t ldb,
             uint64_t* C, int64_t ldc, int64_t m, int64_t k, int64_t n, int64_t block,
             const bmm_options* opt, double* seconds_out);
@@ -166,22 +202,30 @@ int bmm_ooc(int semiring, const uint64_t* A, int64_t lda, const uint64_t* B, int
 int bmm_transpose(const uint64_t* src, int64_t lds, uint64_t* dst, int64_t ldd, int64_t rows,
                   int64_t cols, void* hip_stream);
 /* bmm_basis_change: in place on a rows x (64 * row_words) matrix, the 2 x 2
- * basis change of the self-inverse design at the top `depth` levels:
- * inverse = 0 applies phi (eq. mb-fwdbasisrecurrence), 1 applies chi
- * (eq. mb-revbasisrecurrence).  rows and row_words must be divisible by 2^depth. */
+ * basis change of `scheme` (bmm_scheme) at the top `depth` levels: inverse = 0
+ * applies the forward change (eq. mb-fwdbasisrecurrence for the self-inverse
+ * design, eq. ab-fwdbasisrecurrence for chaining), 1 the inverse change of the
+ * result (eqs. mb-revbasisrecurrence, ab-revbasisrecurrence).  transposed = 1:
+ * X is a right-hand operand stored transposed (its 01 and 10 quadrants trade
+ * places at every level).  The Winograd scheme has no basis change (no-op).
+ * rows and row_words must be divisible by 2^depth. */
 int bmm_basis_change(uint64_t* X, int64_t ld, int64_t rows, int64_t row_words, int depth,
-                     int inverse, void* hip_stream);
+                     int inverse, int scheme, int transposed, void* hip_stream);
 /* bmm_expand: one level (levels = 1) or two merged levels (levels = 2) of the
- * linear combinations of eq. mb-tsrecurrence for `parents` matrices of rows x
- * (64 * words) (parent p at src + p * strideP, pitch ldp).  side 0 = left
- * operand (alpha), 1 = right operand stored transposed (beta).  Children are
- * written compactly to dst: 7^levels per parent, in order. */
-int bmm_expand(int side, int levels, const uint64_t* src, int64_t ldp, int64_t strideP,
-               uint64_t* dst, int64_t rows, int64_t words, int64_t parents, void* hip_stream);
-/* bmm_compress: the inverse step for products (eq. mb-qrecurrence): 7^levels
- * compact children per parent combine into the parents' quadrants. */
-int bmm_compress(int levels, const uint64_t* src, uint64_t* dst, int64_t ldp, int64_t strideP,
-                 int64_t rows, int64_t words, int64_t parents, void* hip_stream);
+ * operand linear combinations of `scheme` (eqs. mb-tsrecurrence,
+ * ab-tsrecurrence, sw-input) for `parents` matrices of rows x (64 * words)
+ * (parent p at src + p * strideP, pitch ldp).  side 0 = left operand (alpha),
+ * 1 = right operand stored transposed (beta).  Children are written compactly
+ * to dst: 7^levels per parent, in order. */
+int bmm_expand(int side, int levels, int scheme, const uint64_t* src, int64_t ldp,
+               int64_t strideP, uint64_t* dst, int64_t rows, int64_t words, int64_t parents,
+               void* hip_stream);
+/* bmm_compress: the combination of products of `scheme` (eqs. mb-qrecurrence,
+ * ab-qrecurrence, sw-output): 7^levels compact children per parent combine
+ * into the parents' quadrants. */
+int bmm_compress(int levels, int scheme, const uint64_t* src, uint64_t* dst, int64_t ldp,
+                 int64_t strideP, int64_t rows, int64_t words, int64_t parents,
+                 void* hip_stream);
 
 /* Number of tile variants of a leaf (valid values of bmm_options.tile are
  * 1..count; 0 = auto), and the C tile (rows x columns) of a variant. */

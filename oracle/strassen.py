@@ -9,7 +9,7 @@ b*w..(b+1)*w, the paper's first-index-major block order 00, 01, 10, 11.
 
 * ``basis(X, d, prog)`` applies a 2x2 basis change at every one of the top d
   levels, i.e. (phi x ... x phi x I_leaf) X, one level at a time (Yates's
-  algorithm, section 2.5; levels may go in any order, ``bottom_up`` picks
+  algorithm, section 2.6; levels may go in any order, ``bottom_up`` picks
   the other one).
 * ``expand_left`` / ``expand_right`` form the seven operand blocks of one
   level (alpha / beta), ``compress`` combines seven product blocks (gamma).

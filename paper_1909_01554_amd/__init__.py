@@ -18,10 +18,11 @@ __all__ = [
     "BmmError", "Options", "GF2", "BOOLEAN", "LEAF_AUTO", "LEAF_VALU", "LEAF_MFMA_I8",
     "LEAF_MFMA_F4",
     "FLAG_ACCUMULATE", "FLAG_B_TRANSPOSED", "FLAG_ALT_BASIS_IO", "FLAG_HOST_OPERANDS",
+    "SCHEME_SELF_INVERSE", "SCHEME_CHAINING", "SCHEME_WINOGRAD",
     "words", "bmm_gf2", "bmm_boolean", "bmm_gf2_strassen", "bmm_gf2_strassen_workspace",
     "bmm_batched", "BatchedPlan", "bmm_transpose", "bmm_basis_change", "bmm_expand",
     "bmm_compress", "bmm_ooc", "bmm_autotune_cubic", "bmm_autotune_leaf",
-    "bmm_autotune_strassen", "bmm_autotune_set", "bmm_autotune_save",
+    "bmm_autotune_strassen", "bmm_autotune_set", "bmm_autotune_batched", "bmm_autotune_save",
     "bmm_autotune_load", "bmm_leaf_tiles", "bmm_leaf_tile_shape", "bmm_version",
     "bmm_finalize", "library_path",
 ]
@@ -32,6 +33,7 @@ FLAG_ACCUMULATE = 0x1
 FLAG_B_TRANSPOSED = 0x2
 FLAG_ALT_BASIS_IO = 0x4
 FLAG_HOST_OPERANDS = 0x8
+SCHEME_SELF_INVERSE, SCHEME_CHAINING, SCHEME_WINOGRAD = 0, 1, 2
 
 _STATUS = {0: "ok", -1: "invalid argument", -2: "unsupported", -3: "workspace too small",
            -4: "out of memory", -5: "device error"}
@@ -58,13 +60,14 @@ _int = ctypes.c_int
 
 
 class Options(ctypes.Structure):
-    """bmm_options: leaf, tile, depth_serial, depth_parallel, block, flags."""
+    """bmm_options: leaf, tile, depth_serial, depth_parallel, block, flags, scheme."""
     _fields_ = [("leaf", _int), ("tile", _int), ("depth_serial", _int),
-                ("depth_parallel", _int), ("block", _i64), ("flags", ctypes.c_uint32)]
+                ("depth_parallel", _int), ("block", _i64), ("flags", ctypes.c_uint32),
+                ("scheme", _int)]
 
     def __init__(self, leaf=LEAF_AUTO, tile=0, depth_serial=-1, depth_parallel=-1, block=0,
-                 flags=0):
-        super().__init__(leaf, tile, depth_serial, depth_parallel, block, flags)
+                 flags=0, scheme=0):
+        super().__init__(leaf, tile, depth_serial, depth_parallel, block, flags, scheme)
 
 
 class Problem(ctypes.Structure):
@@ -90,14 +93,17 @@ _c_strassen_ws = _sig("bmm_gf2_strassen_workspace",
                        ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(_int),
                        ctypes.POINTER(_int)])
 _c_batched = _sig("bmm_batched", [ctypes.POINTER(Problem), _i64, ctypes.POINTER(Options), _vp])
+_c_tune_batched = _sig("bmm_autotune_batched", [ctypes.POINTER(Problem), _i64,
+                                                ctypes.POINTER(_int), ctypes.POINTER(_int),
+                                                ctypes.POINTER(ctypes.c_double)])
 _c_plan_create = _sig("bmm_batched_plan_create", [ctypes.POINTER(Problem), _i64,
                                                   ctypes.POINTER(Options), ctypes.POINTER(_vp)])
 _c_plan_launch = _sig("bmm_batched_plan_launch", [_vp, _vp])
 _c_plan_destroy = _sig("bmm_batched_plan_destroy", [_vp], None)
 _c_transpose = _sig("bmm_transpose", [_vp, _i64, _vp, _i64, _i64, _i64, _vp])
-_c_basis = _sig("bmm_basis_change", [_vp, _i64, _i64, _i64, _int, _int, _vp])
-_c_expand = _sig("bmm_expand", [_int, _int, _vp, _i64, _i64, _vp, _i64, _i64, _i64, _vp])
-_c_compress = _sig("bmm_compress", [_int, _vp, _vp, _i64, _i64, _i64, _i64, _i64, _vp])
+_c_basis = _sig("bmm_basis_change", [_vp, _i64, _i64, _i64, _int, _int, _int, _int, _vp])
+_c_expand = _sig("bmm_expand", [_int, _int, _int, _vp, _i64, _i64, _vp, _i64, _i64, _i64, _vp])
+_c_compress = _sig("bmm_compress", [_int, _int, _vp, _vp, _i64, _i64, _i64, _i64, _i64, _vp])
 _c_ooc = _sig("bmm_ooc", [_int, _vp, _i64, _vp, _i64, _vp, _i64, _i64, _i64, _i64, _i64,
                           ctypes.POINTER(Options), ctypes.POINTER(ctypes.c_double)])
 _c_tune = _sig("bmm_autotune_cubic", [_int, _i64, _i64, _i64, ctypes.POINTER(_int),
@@ -146,10 +152,10 @@ def _ld(t):
 
 
 def _opts(options, flags):
-    o = Options() if options is None else Options(options.leaf, options.tile,
-                                                  options.depth_serial,
-                                                  options.depth_parallel, options.block,
-                                                  options.flags)
+    o = Options()
+    if options is not None:
+        for name, _ in Options._fields_:
+            setattr(o, name, getattr(options, name))
     o.flags |= flags
     return o
 
@@ -186,10 +192,11 @@ def bmm_gf2_strassen_workspace(m, k, n, depth=-1, options=None, alt_basis_io=Fal
 
 
 def bmm_gf2_strassen(A, B, C, m, k, n, workspace, depth=-1, options=None, b_transposed=False,
-                     alt_basis_io=False, stream=None):
-    """C = AB over GF(2) by the self-inverse alternative-basis recursion."""
+                     alt_basis_io=False, accumulate=False, stream=None):
+    """C = AB (or C ^= AB) over GF(2) by the self-inverse alternative-basis recursion."""
     o = _opts(options, (FLAG_B_TRANSPOSED if b_transposed else 0)
-              | (FLAG_ALT_BASIS_IO if alt_basis_io else 0))
+              | (FLAG_ALT_BASIS_IO if alt_basis_io else 0)
+              | (FLAG_ACCUMULATE if accumulate else 0))
     nbytes = workspace.numel() * workspace.element_size()
     _check(_c_strassen(_ptr(A), _ld(A), _ptr(B), _ld(B), _ptr(C), _ld(C), m, k, n, depth,
                        _ptr(workspace), nbytes, ctypes.byref(o), _stream(C, stream)))
@@ -246,27 +253,43 @@ class BatchedPlan:
             pass
 
 
+def bmm_autotune_batched(problems):
+    """Time every batched (leaf, tile) candidate on these problems (outputs are
+    overwritten) and record the fastest for later AUTO plans; returns
+    (leaf, tile, seconds)."""
+    arr = _problems(problems)
+    leaf = _int(0)
+    tile = _int(0)
+    secs = ctypes.c_double(0.0)
+    _check(_c_tune_batched(arr, len(problems), ctypes.byref(leaf), ctypes.byref(tile),
+                           ctypes.byref(secs)))
+    return leaf.value, tile.value, secs.value
+
+
 def bmm_transpose(src, dst, rows, cols, stream=None):
     _check(_c_transpose(_ptr(src), _ld(src), _ptr(dst), _ld(dst), rows, cols,
                         _stream(dst, stream)))
     return dst
 
 
-def bmm_basis_change(X, rows, row_words, depth, inverse=False, stream=None):
-    _check(_c_basis(_ptr(X), _ld(X), rows, row_words, depth, 1 if inverse else 0,
-                    _stream(X, stream)))
+def bmm_basis_change(X, rows, row_words, depth, inverse=False, scheme=SCHEME_SELF_INVERSE,
+                     transposed=False, stream=None):
+    _check(_c_basis(_ptr(X), _ld(X), rows, row_words, depth, 1 if inverse else 0, scheme,
+                    1 if transposed else 0, _stream(X, stream)))
     return X
 
 
-def bmm_expand(side, levels, src, ldp, stride_p, dst, rows, words_, parents, stream=None):
-    _check(_c_expand(side, levels, _ptr(src), ldp, stride_p, _ptr(dst), rows, words_, parents,
-                     _stream(dst, stream)))
+def bmm_expand(side, levels, src, ldp, stride_p, dst, rows, words_, parents,
+               scheme=SCHEME_SELF_INVERSE, stream=None):
+    _check(_c_expand(side, levels, scheme, _ptr(src), ldp, stride_p, _ptr(dst), rows, words_,
+                     parents, _stream(dst, stream)))
     return dst
 
 
-def bmm_compress(levels, src, dst, ldp, stride_p, rows, words_, parents, stream=None):
-    _check(_c_compress(levels, _ptr(src), _ptr(dst), ldp, stride_p, rows, words_, parents,
-                       _stream(dst, stream)))
+def bmm_compress(levels, src, dst, ldp, stride_p, rows, words_, parents,
+                 scheme=SCHEME_SELF_INVERSE, stream=None):
+    _check(_c_compress(levels, scheme, _ptr(src), _ptr(dst), ldp, stride_p, rows, words_,
+                       parents, _stream(dst, stream)))
     return dst
 
 

@@ -117,6 +117,17 @@ struct TuneVal {
 std::map<TuneKey, TuneVal> g_tune;
 // Strassen (depth, serial depth) per shape, from bmm_autotune_strassen.
 std::map<std::tuple<int64_t, int64_t, int64_t>, std::pair<int, int>> g_depth;
+// Batched plans: (problem count, floor(log2(total ops))) -> (leaf, tile).
+std::map<std::pair<int64_t, int>, std::pair<int, int>> g_batched;
+
+int ops_bucket(double ops) {
+  int b = 0;
+  while (ops >= 2.0 && b < 200) {
+    ops *= 0.5;
+    ++b;
+  }
+  return b;
+}
 
 int64_t batch_bucket(int64_t b) {
   int64_t q = 1;
@@ -222,6 +233,7 @@ struct Level {
 
 struct StrassenPlan {
   int depth = 0, ds = 0, dp = 0;
+  int scheme = BMM_SCHEME_SELF_INVERSE;
   int64_t m = 0, kw = 0, n = 0, nw = 0;
   size_t ahat = 0, bhat = 0;
   std::vector<Level> serial;         // levels 1..ds (index l-1)
@@ -232,11 +244,16 @@ struct StrassenPlan {
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// alt_io: A is used in place (already in the alternative basis), so no copy of it
+// is planned.  stage_b = false: the caller supplies B^T in the alternative basis.
 int make_plan(int64_t m, int64_t k, int64_t n, int depth, const bmm_options& o, bool alt_io,
-              StrassenPlan* plan) {
+              StrassenPlan* plan, bool stage_b = true) {
   if (m < 0 || k < 0 || n < 0) return fail(BMM_E_INVAL, "negative size");
   if (depth < -1 || depth > 12) return fail(BMM_E_INVAL, "depth %d out of range", depth);
+  if (o.scheme < BMM_SCHEME_SELF_INVERSE || o.scheme > BMM_SCHEME_WINOGRAD)
+    return fail(BMM_E_INVAL, "unknown scheme %d", o.scheme);
   StrassenPlan P;
+  P.scheme = o.scheme;
   P.m = m;
   P.kw = words_of(k);
   P.n = n;
@@ -289,8 +306,10 @@ int make_plan(int64_t m, int64_t k, int64_t n, int depth, const bmm_options& o, 
     P.ahat = off;
     off = align_up(off + (size_t)m * P.kw * 8);
   }
-  P.bhat = off;
-  off = align_up(off + (size_t)n * P.kw * 8);
+  if (stage_b) {
+    P.bhat = off;
+    off = align_up(off + (size_t)n * P.kw * 8);
+  }
   for (int l = 1; l <= ds; ++l) {
     const int64_t M = m >> l, KW = P.kw >> l, N = n >> l, NW = P.nw >> l;
     Level L;
@@ -333,8 +352,9 @@ struct StrassenRun {
 
   uint64_t* at(size_t off) const { return reinterpret_cast<uint64_t*>(ws + off); }
 
+  // acc = 1: the result is XORed into Q (only ever set for the top-level output).
   int parallel(int level, const uint64_t* T, int64_t ldT, const uint64_t* S, int64_t ldS,
-               uint64_t* Q, int64_t ldQ) const {
+               uint64_t* Q, int64_t ldQ, int acc) const {
     const StrassenPlan& p = *P;
     const uint64_t* curT = T;
     const uint64_t* curS = S;
@@ -346,11 +366,15 @@ struct StrassenRun {
       const int64_t M = p.m >> lvl, KW = p.kw >> lvl, N = p.n >> lvl;
       const Level& L = p.par[i];
       if (step == 2) {
-        HIP_TRY(launch_expand2(0, curT, pitchT, strideT, at(L.T), M, KW, inst, s), "expand2 T");
-        HIP_TRY(launch_expand2(1, curS, pitchS, strideS, at(L.S), N, KW, inst, s), "expand2 S");
+        HIP_TRY(launch_expand2(0, curT, pitchT, strideT, at(L.T), M, KW, inst, s, p.scheme),
+                "expand2 T");
+        HIP_TRY(launch_expand2(1, curS, pitchS, strideS, at(L.S), N, KW, inst, s, p.scheme),
+                "expand2 S");
       } else {
-        HIP_TRY(launch_expand(0, curT, pitchT, strideT, at(L.T), M, KW, inst, s), "expand T");
-        HIP_TRY(launch_expand(1, curS, pitchS, strideS, at(L.S), N, KW, inst, s), "expand S");
+        HIP_TRY(launch_expand(0, curT, pitchT, strideT, at(L.T), M, KW, inst, s, p.scheme),
+                "expand T");
+        HIP_TRY(launch_expand(1, curS, pitchS, strideS, at(L.S), N, KW, inst, s, p.scheme),
+                "expand S");
       }
       lvl += step;
       inst *= step == 2 ? 49 : 7;
@@ -365,7 +389,7 @@ struct StrassenRun {
     uint64_t* leafQ = p.par.empty() ? Q : at(p.par.back().Q);
     const int64_t ldLQ = p.par.empty() ? ldQ : NW;
     LeafBatch lb{curT, pitchT, strideT, curS, pitchS, strideS, leafQ, ldLQ, M * NW,
-                 M, (p.kw >> lvl) * 64, N, inst, 0};
+                 M, (p.kw >> lvl) * 64, N, inst, p.par.empty() ? acc : 0};
     BMM_TRY(run_leaf(BMM_GF2, leaf, tile, lb, s));
     // compress back up
     for (int i = (int)p.psteps.size() - 1; i >= 0; --i) {
@@ -385,27 +409,30 @@ struct StrassenRun {
         strideD = (p.m >> lvl) * ldd;
       }
       const int64_t M2 = p.m >> lvl, NW2 = p.nw >> lvl;
+      const int a = i == 0 ? acc : 0;
       if (step == 2)
-        HIP_TRY(launch_compress2(src, dst, ldd, strideD, M2, NW2, inst, s), "compress2");
+        HIP_TRY(launch_compress2(src, dst, ldd, strideD, M2, NW2, inst, s, a, p.scheme),
+                "compress2");
       else
-        HIP_TRY(launch_compress(src, dst, ldd, strideD, M2, NW2, inst, s), "compress");
+        HIP_TRY(launch_compress(src, dst, ldd, strideD, M2, NW2, inst, s, a, p.scheme),
+                "compress");
     }
     return BMM_OK;
   }
 
   int solve(int level, const uint64_t* T, int64_t ldT, const uint64_t* S, int64_t ldS,
-            uint64_t* Q, int64_t ldQ) const {
+            uint64_t* Q, int64_t ldQ, int acc) const {
     const StrassenPlan& p = *P;
-    if (level >= p.ds) return parallel(level, T, ldT, S, ldS, Q, ldQ);
+    if (level >= p.ds) return parallel(level, T, ldT, S, ldS, Q, ldQ, acc);
     const int64_t M = p.m >> level, KW = p.kw >> level, N = p.n >> level, NW = p.nw >> level;
     const Level& L = p.serial[level];
-    HIP_TRY(launch_expand(0, T, ldT, 0, at(L.T), M, KW, 1, s), "serial expand T");
-    HIP_TRY(launch_expand(1, S, ldS, 0, at(L.S), N, KW, 1, s), "serial expand S");
+    HIP_TRY(launch_expand(0, T, ldT, 0, at(L.T), M, KW, 1, s, p.scheme), "serial expand T");
+    HIP_TRY(launch_expand(1, S, ldS, 0, at(L.S), N, KW, 1, s, p.scheme), "serial expand S");
     const int64_t cT = (M / 2) * (KW / 2), cS = (N / 2) * (KW / 2), cQ = (M / 2) * (NW / 2);
     for (int h = 0; h < 7; ++h)
       BMM_TRY(solve(level + 1, at(L.T) + h * cT, KW / 2, at(L.S) + h * cS, KW / 2,
-                    at(L.Q) + h * cQ, NW / 2));
-    HIP_TRY(launch_compress(at(L.Q), Q, ldQ, 0, M, NW, 1, s), "serial compress");
+                    at(L.Q) + h * cQ, NW / 2, 0));
+    HIP_TRY(launch_compress(at(L.Q), Q, ldQ, 0, M, NW, 1, s, acc, p.scheme), "serial compress");
     return BMM_OK;
   }
 };
@@ -422,6 +449,7 @@ void bmm_options_init(bmm_options* opt) {
   opt->depth_parallel = -1;
   opt->block = 0;
   opt->flags = 0;
+  opt->scheme = BMM_SCHEME_SELF_INVERSE;
 }
 
 int bmm_gf2(const uint64_t* A, int64_t lda, const uint64_t* B, int64_t ldb, uint64_t* C,
@@ -457,14 +485,13 @@ int bmm_gf2_strassen(const uint64_t* A, int64_t lda, const uint64_t* B, int64_t 
     return fail(BMM_E_UNSUPPORTED, "host operands: use the out-of-core entry (bmm_ooc)");
   const bool b_t = (o.flags & BMM_FLAG_B_TRANSPOSED) != 0;
   const bool alt = (o.flags & BMM_FLAG_ALT_BASIS_IO) != 0;
-  if (o.flags & BMM_FLAG_ACCUMULATE)
-    return fail(BMM_E_UNSUPPORTED, "accumulate is not supported by the Strassen product");
+  const int acc = (o.flags & BMM_FLAG_ACCUMULATE) ? 1 : 0;
   BMM_TRY(validate_product(A, lda, B, ldb, C, ldc, m, k, n, b_t));
   StrassenPlan P;
   BMM_TRY(make_plan(m, k, n, depth, o, alt, &P));
   if (m == 0 || n == 0) return BMM_OK;
   hipStream_t s = (hipStream_t)hip_stream;
-  if (k == 0) return check_hip(launch_zero(C, ldc, m, P.nw, s), "zero");
+  if (k == 0) return acc ? BMM_OK : check_hip(launch_zero(C, ldc, m, P.nw, s), "zero");
   if (!workspace || workspace_bytes < P.bytes)
     return fail(BMM_E_WORKSPACE, "workspace of %zu bytes needed, %zu given", P.bytes,
                 workspace_bytes);
@@ -486,8 +513,8 @@ int bmm_gf2_strassen(const uint64_t* A, int64_t lda, const uint64_t* B, int64_t 
   if (!alt) {
     uint64_t* Ah = reinterpret_cast<uint64_t*>(ws + P.ahat);
     HIP_TRY(launch_copy(A, lda, Ah, P.kw, m, P.kw, s), "copy A");
-    HIP_TRY(launch_basis(Ah, P.kw, 0, m, P.kw, 1, P.depth, 0, s), "basis A");
-    HIP_TRY(launch_basis(BT, P.kw, 0, n, P.kw, 1, P.depth, 0, s), "basis B");
+    HIP_TRY(launch_basis(Ah, P.kw, 0, m, P.kw, 1, P.depth, 0, s, P.scheme, 0), "basis A");
+    HIP_TRY(launch_basis(BT, P.kw, 0, n, P.kw, 1, P.depth, 0, s, P.scheme, 1), "basis B");
     T0 = Ah;
     ldT0 = P.kw;
   }
@@ -497,10 +524,71 @@ int bmm_gf2_strassen(const uint64_t* A, int64_t lda, const uint64_t* B, int64_t 
   for (int i = 0; i < P.dp; ++i) leaves *= 7;
   pick_leaf(BMM_GF2, m / u, k / u, n / u, leaves, o, &leaf, &tile);
   StrassenRun run{&P, ws, leaf, tile, s};
-  BMM_TRY(run.solve(0, T0, ldT0, BT, P.kw, C, ldc));
-  if (!alt) HIP_TRY(launch_basis(C, ldc, 0, m, P.nw, 1, P.depth, 1, s), "basis C");
+  // C ^= chi(core) is computed as chi(chi^-1(C) ^ core): C is taken to the
+  // alternative basis and back (chi^-1 is chi itself for the self-inverse design
+  // and the forward change for the chaining one).
+  if (!alt && acc) HIP_TRY(to_alt_basis(C, ldc, m, P.nw, P.depth, P.scheme, s), "basis C");
+  BMM_TRY(run.solve(0, T0, ldT0, BT, P.kw, C, ldc, acc));
+  if (!alt) HIP_TRY(launch_basis(C, ldc, 0, m, P.nw, 1, P.depth, 1, s, P.scheme), "basis C");
   return BMM_OK;
 }
+
+}  // extern "C"
+
+namespace bmm {
+
+bool batched_tuned(int64_t count, double ops, int* leaf, int* tile) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  auto it = g_batched.find({count, ops_bucket(ops)});
+  if (it == g_batched.end()) return false;
+  *leaf = it->second.first;
+  *tile = it->second.second;
+  return true;
+}
+
+void batched_tune_set(int64_t count, double ops, int leaf, int tile) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  g_batched[{count, ops_bucket(ops)}] = {leaf, tile};
+}
+
+hipError_t to_alt_basis(uint64_t* C, int64_t ldc, int64_t rows, int64_t words, int depth,
+                        int scheme, hipStream_t s) {
+  // chaining: the forward change is the inverse of the result's change;
+  // self-inverse: the result's change is its own inverse
+  if (scheme == BMM_SCHEME_CHAINING)
+    return launch_basis(C, ldc, 0, rows, words, 1, depth, 0, s, scheme, 0);
+  return launch_basis(C, ldc, 0, rows, words, 1, depth, 1, s, scheme, 0);
+}
+
+int strassen_alt_plan(int64_t m, int64_t k, int64_t n, int depth, const bmm_options& o,
+                      size_t* bytes, int* depth_out) {
+  StrassenPlan P;
+  BMM_TRY(make_plan(m, k, n, depth, o, true, &P, false));
+  *bytes = P.bytes;
+  *depth_out = P.depth;
+  return BMM_OK;
+}
+
+int strassen_alt(const uint64_t* Ahat, int64_t lda, const uint64_t* BThat, int64_t ldbt,
+                 uint64_t* C, int64_t ldc, int64_t m, int64_t k, int64_t n, int depth,
+                 void* ws, size_t bytes, const bmm_options& o, int accumulate, hipStream_t s) {
+  StrassenPlan P;
+  BMM_TRY(make_plan(m, k, n, depth, o, true, &P, false));
+  if (bytes < P.bytes) return fail(BMM_E_WORKSPACE, "workspace of %zu bytes needed", P.bytes);
+  if (m == 0 || n == 0 || (k == 0 && accumulate)) return BMM_OK;
+  if (k == 0) return check_hip(launch_zero(C, ldc, m, P.nw, s), "zero");
+  int leaf, tile;
+  const int64_t u = (int64_t)1 << P.depth;
+  int64_t leaves = 1;
+  for (int i = 0; i < P.dp; ++i) leaves *= 7;
+  pick_leaf(BMM_GF2, m / u, k / u, n / u, leaves, o, &leaf, &tile);
+  StrassenRun run{&P, static_cast<char*>(ws), leaf, tile, s};
+  return run.solve(0, Ahat, lda, BThat, ldbt, C, ldc, accumulate);
+}
+
+}  // namespace bmm
+
+extern "C" {
 
 int bmm_transpose(const uint64_t* src, int64_t lds, uint64_t* dst, int64_t ldd, int64_t rows,
                   int64_t cols, void* hip_stream) {
@@ -516,45 +604,57 @@ int bmm_transpose(const uint64_t* src, int64_t lds, uint64_t* dst, int64_t ldd, 
 }
 
 int bmm_basis_change(uint64_t* X, int64_t ld, int64_t rows, int64_t row_words, int depth,
-                     int inverse, void* hip_stream) {
+                     int inverse, int scheme, int transposed, void* hip_stream) {
   if (rows < 0 || row_words < 0 || depth < 0 || depth > 20)
     return fail(BMM_E_INVAL, "bad size or depth");
+  if (scheme < BMM_SCHEME_SELF_INVERSE || scheme > BMM_SCHEME_WINOGRAD)
+    return fail(BMM_E_INVAL, "unknown scheme %d", scheme);
   if (rows == 0 || row_words == 0 || depth == 0) return BMM_OK;
   if (!X || ld < row_words) return fail(BMM_E_INVAL, "null pointer or pitch too small");
   const int64_t u = (int64_t)1 << depth;
   if (rows % u || row_words % u)
     return fail(BMM_E_UNSUPPORTED, "rows and row words must be divisible by 2^depth");
   return check_hip(launch_basis(X, ld, 0, rows, row_words, 1, depth, inverse ? 1 : 0,
-                                (hipStream_t)hip_stream),
+                                (hipStream_t)hip_stream, scheme, transposed ? 1 : 0),
                    "basis change");
 }
 
-int bmm_expand(int side, int levels, const uint64_t* src, int64_t ldp, int64_t strideP,
-               uint64_t* dst, int64_t rows, int64_t words, int64_t parents, void* hip_stream) {
+int bmm_expand(int side, int levels, int scheme, const uint64_t* src, int64_t ldp,
+               int64_t strideP, uint64_t* dst, int64_t rows, int64_t words, int64_t parents,
+               void* hip_stream) {
   if ((side != 0 && side != 1) || (levels != 1 && levels != 2))
     return fail(BMM_E_INVAL, "side must be 0/1 and levels 1/2");
+  if (scheme < BMM_SCHEME_SELF_INVERSE || scheme > BMM_SCHEME_WINOGRAD)
+    return fail(BMM_E_INVAL, "unknown scheme %d", scheme);
   if (rows < 0 || words < 0 || parents < 0) return fail(BMM_E_INVAL, "negative size");
   if (rows == 0 || words == 0 || parents == 0) return BMM_OK;
   const int64_t u = levels == 2 ? 4 : 2;
   if (rows % u || words % u) return fail(BMM_E_UNSUPPORTED, "sizes must be divisible by %ld", (long)u);
   if (!src || !dst || ldp < words) return fail(BMM_E_INVAL, "null pointer or pitch too small");
   hipStream_t s = (hipStream_t)hip_stream;
-  return check_hip(levels == 2 ? launch_expand2(side, src, ldp, strideP, dst, rows, words, parents, s)
-                               : launch_expand(side, src, ldp, strideP, dst, rows, words, parents, s),
+  return check_hip(levels == 2 ? launch_expand2(side, src, ldp, strideP, dst, rows, words,
+                                                parents, s, scheme)
+                               : launch_expand(side, src, ldp, strideP, dst, rows, words,
+                                               parents, s, scheme),
                    "expand");
 }
 
-int bmm_compress(int levels, const uint64_t* src, uint64_t* dst, int64_t ldp, int64_t strideP,
-                 int64_t rows, int64_t words, int64_t parents, void* hip_stream) {
+int bmm_compress(int levels, int scheme, const uint64_t* src, uint64_t* dst, int64_t ldp,
+                 int64_t strideP, int64_t rows, int64_t words, int64_t parents,
+                 void* hip_stream) {
   if (levels != 1 && levels != 2) return fail(BMM_E_INVAL, "levels must be 1 or 2");
+  if (scheme < BMM_SCHEME_SELF_INVERSE || scheme > BMM_SCHEME_WINOGRAD)
+    return fail(BMM_E_INVAL, "unknown scheme %d", scheme);
   if (rows < 0 || words < 0 || parents < 0) return fail(BMM_E_INVAL, "negative size");
   if (rows == 0 || words == 0 || parents == 0) return BMM_OK;
   const int64_t u = levels == 2 ? 4 : 2;
   if (rows % u || words % u) return fail(BMM_E_UNSUPPORTED, "sizes must be divisible by %ld", (long)u);
   if (!src || !dst || ldp < words) return fail(BMM_E_INVAL, "null pointer or pitch too small");
   hipStream_t s = (hipStream_t)hip_stream;
-  return check_hip(levels == 2 ? launch_compress2(src, dst, ldp, strideP, rows, words, parents, s)
-                               : launch_compress(src, dst, ldp, strideP, rows, words, parents, s),
+  return check_hip(levels == 2 ? launch_compress2(src, dst, ldp, strideP, rows, words, parents,
+                                                  s, 0, scheme)
+                               : launch_compress(src, dst, ldp, strideP, rows, words, parents,
+                                                 s, 0, scheme),
                    "compress");
 }
 
@@ -628,11 +728,9 @@ int bmm_autotune_leaf(int semiring, int64_t m, int64_t k, int64_t n, int64_t bat
     for (int t = 1; t <= MFMA_NUM_TILES; ++t) cands.push_back({BMM_LEAF_MFMA_F4, t});
   for (auto [leaf, tile] : cands) {
     LeafBatch p{A, kw, m * kw, BT, kw, n * kw, C, nw, m * nw, m, k, n, nb, 0};
-    rc = run_leaf(semiring, leaf, tile, p, nullptr);  // warm-up
-    if (rc != BMM_OK) break;
-    const int reps = 3;
+    // a timed warm-up; launches longer than 0.2 s are timed once, shorter ones 3 more times
     (void)hipEventRecord(e0, nullptr);
-    for (int r = 0; r < reps && rc == BMM_OK; ++r) rc = run_leaf(semiring, leaf, tile, p, nullptr);
+    rc = run_leaf(semiring, leaf, tile, p, nullptr);
     (void)hipEventRecord(e1, nullptr);
     if (rc != BMM_OK) break;
     if (hipEventSynchronize(e1) != hipSuccess) {
@@ -641,6 +739,20 @@ int bmm_autotune_leaf(int semiring, int64_t m, int64_t k, int64_t n, int64_t bat
     }
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, e0, e1);
+    int reps = 1;
+    if (ms < 200.f) {
+      reps = 3;
+      (void)hipEventRecord(e0, nullptr);
+      for (int r = 0; r < reps && rc == BMM_OK; ++r)
+        rc = run_leaf(semiring, leaf, tile, p, nullptr);
+      (void)hipEventRecord(e1, nullptr);
+      if (rc != BMM_OK) break;
+      if (hipEventSynchronize(e1) != hipSuccess) {
+        rc = check_hip(hipGetLastError(), "autotune sync");
+        break;
+      }
+      (void)hipEventElapsedTime(&ms, e0, e1);
+    }
     const double sec = ms * 1e-3 / reps;
     if (sec < best_of[leaf]) {
       best_of[leaf] = sec;
@@ -746,7 +858,8 @@ int bmm_autotune_save(const char* path) {
   std::lock_guard<std::mutex> lock(g_mu);
   f << "# bmm autotune table\n"
        "# leaf semiring m k n batch_bucket best_leaf tile_valu tile_mfma_i8 tile_mfma_f4\n"
-       "# depth m k n depth depth_serial\n";
+       "# depth m k n depth depth_serial\n"
+       "# batched count log2_ops leaf tile\n";
   for (auto& [key, val] : g_tune)
     f << "leaf " << key.semiring << ' ' << key.m << ' ' << key.k << ' ' << key.n << ' '
       << key.batch << ' ' << val.best_leaf << ' ' << val.tile[1] << ' ' << val.tile[2] << ' '
@@ -754,6 +867,9 @@ int bmm_autotune_save(const char* path) {
   for (auto& [key, val] : g_depth)
     f << "depth " << std::get<0>(key) << ' ' << std::get<1>(key) << ' ' << std::get<2>(key)
       << ' ' << val.first << ' ' << val.second << '\n';
+  for (auto& [key, val] : g_batched)
+    f << "batched " << key.first << ' ' << key.second << ' ' << val.first << ' ' << val.second
+      << '\n';
   return f ? BMM_OK : fail(BMM_E_INVAL, "write failed: %s", path);
 }
 
@@ -783,6 +899,12 @@ int bmm_autotune_load(const char* path) {
       if (d < 0 || ds < 0 || ds > d) return fail(BMM_E_INVAL, "bad depth line: %s", line.c_str());
       std::lock_guard<std::mutex> lock(g_mu);
       g_depth[{m, k, n}] = {d, ds};
+    } else if (sscanf(line.c_str(), "batched %lld %d %d %d", &m, &d, &leaf, &t1) == 4) {
+      if (m <= 0 || d < 0 || (leaf != BMM_LEAF_MFMA_I8 && leaf != BMM_LEAF_MFMA_F4) ||
+          (t1 != 1 && t1 != 2))
+        return fail(BMM_E_INVAL, "bad batched line: %s", line.c_str());
+      std::lock_guard<std::mutex> lock(g_mu);
+      g_batched[{m, d}] = {leaf, t1};
     } else {
       return fail(BMM_E_INVAL, "bad line in %s: %s", path, line.c_str());
     }
@@ -821,6 +943,7 @@ void bmm_finalize(void) {
   g_scratch.clear();
   g_tune.clear();
   g_depth.clear();
+  g_batched.clear();
 }
 
 }  // extern "C"

@@ -25,6 +25,8 @@ struct Plan {
   int64_t total_tiles = 0;
   int grid = 0;
   int device = 0;
+  int leaf = BMM_LEAF_MFMA_I8;  // BMM_LEAF_MFMA_I8 or BMM_LEAF_MFMA_F4
+  int tile = 2;                 // 1: 128 x 64 per wave, 2: 64 x 64
 };
 
 int validate_problem(const bmm_problem& p, int64_t i) {
@@ -45,20 +47,40 @@ int validate_problem(const bmm_problem& p, int64_t i) {
   return BMM_OK;
 }
 
-int build_plan(const bmm_problem* problems, int64_t count, Plan* out) {
+int build_plan(const bmm_problem* problems, int64_t count, const bmm_options* opt, Plan* out) {
   if (count < 0 || (count > 0 && !problems)) return bfail(BMM_E_INVAL, "bad problem list");
   std::vector<int64_t> order;
+  double ops = 0;
+  int64_t kmax = 0;
   for (int64_t i = 0; i < count; ++i) {
     int rc = validate_problem(problems[i], i);
     if (rc != BMM_OK) return rc;
     if (!problems[i].b_transposed)
       return bfail(BMM_E_INVAL, "problem %ld: plans need B passed transposed", (long)i);
     if (problems[i].m > 0 && problems[i].n > 0) order.push_back(i);
+    ops += 2.0 * problems[i].m * problems[i].k * problems[i].n;
+    kmax = std::max(kmax, problems[i].k);
   }
+  // leaf kind and tile: explicit options, else the autotuner's record for plans of this
+  // count and total work, else int8 with 64 x 64 tiles
+  int leaf = opt ? opt->leaf : BMM_LEAF_AUTO;
+  int tile = opt ? opt->tile : 0;
+  int tl = 0, tt = 0;
+  if ((leaf == BMM_LEAF_AUTO || tile <= 0) && batched_tuned(count, ops, &tl, &tt)) {
+    if (leaf == BMM_LEAF_AUTO) leaf = tl;
+    if (tile <= 0) tile = tt;
+  }
+  if (leaf == BMM_LEAF_AUTO) leaf = BMM_LEAF_MFMA_I8;
+  if (tile <= 0) tile = 2;
+  if (leaf != BMM_LEAF_MFMA_I8 && leaf != BMM_LEAF_MFMA_F4)
+    return bfail(BMM_E_UNSUPPORTED, "batched plans run the int8 or fp4 matrix-core leaf");
+  if (tile != 1 && tile != 2) return bfail(BMM_E_INVAL, "batched tile must be 1 or 2");
+  if (leaf == BMM_LEAF_MFMA_F4 && kmax >= ((int64_t)1 << 24))
+    return bfail(BMM_E_UNSUPPORTED, "the fp4 leaf counts exactly only for k < 2^24");
   std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
     return problems[a].k > problems[b].k;
   });
-  const int TR = batched_tile_rows(), TC = batched_tile_cols();
+  const int TR = batched_tile_rows(tile), TC = batched_tile_cols(tile);
   std::vector<BatchedDesc> host;
   int64_t tiles = 0;
   for (int64_t i : order) {
@@ -82,13 +104,15 @@ int build_plan(const bmm_problem* problems, int64_t count, Plan* out) {
   if (tiles >= ((int64_t)1 << 32) - ((int64_t)1 << 20))
     return bfail(BMM_E_UNSUPPORTED, "batched plans hold fewer than 2^32 tiles (%ld)", (long)tiles);
   Plan P;
+  P.leaf = leaf;
+  P.tile = tile;
   P.count = (int64_t)host.size();
   P.total_tiles = tiles;
   std::vector<uint32_t> begins;
   for (const auto& d : host) begins.push_back((uint32_t)d.tile_begin);
   if (hipGetDevice(&P.device) != hipSuccess) return bfail(BMM_E_DEVICE, "hipGetDevice");
   int cus = 256;
-  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, P.device);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, P.device);
   P.grid = std::max(1, cus * 4);
   if (P.count > 0) {
     if (hipMalloc((void**)&P.descs, sizeof(BatchedDesc) * host.size()) != hipSuccess ||
@@ -118,10 +142,10 @@ int build_plan(const bmm_problem* problems, int64_t count, Plan* out) {
 extern "C" {
 
 int bmm_batched_plan_create(const bmm_problem* problems, int64_t count,
-                            const bmm_options* /*opt*/, void** plan_out) {
+                            const bmm_options* opt, void** plan_out) {
   if (!plan_out) return bfail(BMM_E_INVAL, "null plan_out");
   Plan* P = new Plan();
-  int rc = build_plan(problems, count, P);
+  int rc = build_plan(problems, count, opt, P);
   if (rc != BMM_OK) {
     delete P;
     return rc;
@@ -133,8 +157,9 @@ int bmm_batched_plan_create(const bmm_problem* problems, int64_t count,
 int bmm_batched_plan_launch(void* plan, void* hip_stream) {
   if (!plan) return bfail(BMM_E_INVAL, "null plan");
   Plan* P = static_cast<Plan*>(plan);
-  hipError_t e = launch_batched_persistent(P->descs, P->begins, P->count, P->total_tiles,
-                                           P->counter, P->grid, (hipStream_t)hip_stream);
+  hipError_t e = launch_batched_persistent(
+      P->descs, P->begins, P->count, P->total_tiles, P->counter, P->grid, P->tile,
+      P->leaf == BMM_LEAF_MFMA_F4 ? 1 : 0, (hipStream_t)hip_stream);
   if (e != hipSuccess) return bfail(BMM_E_DEVICE, "batched launch: %s", hipGetErrorString(e));
   return BMM_OK;
 }
@@ -153,6 +178,59 @@ void bmm_batched_plan_destroy(void* plan) {
     (void)hipSetDevice(cur);
   }
   delete P;
+}
+
+int bmm_autotune_batched(const bmm_problem* problems, int64_t count, int* leaf_out,
+                         int* tile_out, double* seconds_out) {
+  if (count <= 0 || !problems) return bfail(BMM_E_INVAL, "bad problem list");
+  double ops = 0;
+  for (int64_t i = 0; i < count; ++i) ops += 2.0 * problems[i].m * problems[i].k * problems[i].n;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return bfail(BMM_E_DEVICE, "event create");
+  double best = 1e30;
+  int best_leaf = BMM_LEAF_MFMA_I8, best_tile = 2, rc = BMM_OK;
+  for (int leaf : {BMM_LEAF_MFMA_I8, BMM_LEAF_MFMA_F4}) {
+    for (int tile : {1, 2}) {
+      bmm_options o;
+      bmm_options_init(&o);
+      o.leaf = leaf;
+      o.tile = tile;
+      void* plan = nullptr;
+      rc = bmm_batched_plan_create(problems, count, &o, &plan);
+      if (rc == BMM_E_UNSUPPORTED) {  // e.g. fp4 with k >= 2^24: not a candidate
+        rc = BMM_OK;
+        continue;
+      }
+      if (rc != BMM_OK) break;
+      rc = bmm_batched_plan_launch(plan, nullptr);  // warm-up
+      if (rc == BMM_OK) {
+        (void)hipEventRecord(e0, nullptr);
+        rc = bmm_batched_plan_launch(plan, nullptr);
+        (void)hipEventRecord(e1, nullptr);
+      }
+      float ms = 0.f;
+      if (rc == BMM_OK && (hipEventSynchronize(e1) != hipSuccess ||
+                           hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        rc = bfail(BMM_E_DEVICE, "autotune timing: %s", hipGetErrorString(hipGetLastError()));
+      bmm_batched_plan_destroy(plan);
+      if (rc != BMM_OK) break;
+      if (ms * 1e-3 < best) {
+        best = ms * 1e-3;
+        best_leaf = leaf;
+        best_tile = tile;
+      }
+    }
+    if (rc != BMM_OK) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != BMM_OK) return rc;
+  batched_tune_set(count, ops, best_leaf, best_tile);
+  if (leaf_out) *leaf_out = best_leaf;
+  if (tile_out) *tile_out = best_tile;
+  if (seconds_out) *seconds_out = best;
+  return BMM_OK;
 }
 
 int bmm_batched(const bmm_problem* problems, int64_t count, const bmm_options* opt,
@@ -187,7 +265,7 @@ int bmm_batched(const bmm_problem* problems, int64_t count, const bmm_options* o
       uint64_t* bt = stage + off / 8;
       hipError_t e = launch_transpose(p.B, p.ldb, 0, bt, kw, 0, p.k, p.n, 1, s);
       if (e != hipSuccess) {
-        hipFree(stage);
+        (void)hipFree(stage);
         return bfail(BMM_E_DEVICE, "transpose: %s", hipGetErrorString(e));
       }
       p.B = bt;
@@ -206,7 +284,7 @@ int bmm_batched(const bmm_problem* problems, int64_t count, const bmm_options* o
   bmm_batched_plan_destroy(plan);
   if (stage) {
     (void)hipStreamSynchronize(s);
-    hipFree(stage);
+    (void)hipFree(stage);
   }
   return rc;
 }

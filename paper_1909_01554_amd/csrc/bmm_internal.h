@@ -78,32 +78,37 @@ hipError_t launch_transpose(const uint64_t* src, int64_t lds, int64_t strideS,
                             uint64_t* dst, int64_t ldd, int64_t strideD,
                             int64_t rows, int64_t cols, int64_t batch, hipStream_t s);
 
-// 2x2 basis change of the self-inverse design applied at the top `depth`
-// levels of every matrix of a batch (rows and row words divisible by 2^depth),
-// in place.  inverse = 0: phi (forward, both operands), 1: chi (result).
+// 2x2 basis change of a scheme (bmm_scheme) applied at the top `depth` levels
+// of every matrix of a batch (rows and row words divisible by 2^depth), in
+// place.  inverse = 0: the forward change (both operands; transposed = 1 for
+// an operand stored transposed), 1: the inverse change (result).  The
+// Winograd scheme has none (no-op).
 hipError_t launch_basis(uint64_t* X, int64_t ld, int64_t stride, int64_t rows,
                         int64_t row_words, int64_t batch, int depth, int inverse,
-                        hipStream_t s);
+                        hipStream_t s, int scheme = 0, int transposed = 0);
 
-// One recursion level.  Parent p of a batch (rows x words, pitch ldp, stride
-// strideP) expands into 7 children stored contiguously: child (p, h) is
+// One recursion level of a scheme (bmm_scheme).  Parent p of a batch (rows x
+// words, pitch ldp, stride strideP) expands into 7 children stored
+// contiguously: child (p, h) is
 // matrix 7p + h of `dst`, each (rows/2) x (words/2) with pitch words/2.
 // side 0: left operand (alpha), 1: right operand stored transposed (beta with
 // the 01 and 10 quadrants swapped).
 hipError_t launch_expand(int side, const uint64_t* src, int64_t ldp, int64_t strideP,
                          uint64_t* dst, int64_t rows, int64_t words, int64_t parents,
-                         hipStream_t s);
+                         hipStream_t s, int scheme = 0);
 // Two recursion levels at once (49 grandchildren per parent, index 49p + 7h1 + h2).
 hipError_t launch_expand2(int side, const uint64_t* src, int64_t ldp, int64_t strideP,
                           uint64_t* dst, int64_t rows, int64_t words, int64_t parents,
-                          hipStream_t s);
+                          hipStream_t s, int scheme = 0);
 // Inverse of the above for the products: 7 children (compact, (rows/2) x
-// (words/2)) of parent p combine by gamma into the parent's 4 quadrants.
+// (words/2)) of parent p combine by gamma into the parent's 4 quadrants
+// (accumulate = 1: XORed into the parent instead of overwriting it).
 hipError_t launch_compress(const uint64_t* src, uint64_t* dst, int64_t ldp, int64_t strideP,
-                           int64_t rows, int64_t words, int64_t parents, hipStream_t s);
+                           int64_t rows, int64_t words, int64_t parents, hipStream_t s,
+                           int accumulate = 0, int scheme = 0);
 hipError_t launch_compress2(const uint64_t* src, uint64_t* dst, int64_t ldp,
                             int64_t strideP, int64_t rows, int64_t words, int64_t parents,
-                            hipStream_t s);
+                            hipStream_t s, int accumulate = 0, int scheme = 0);
 
 // Copy a batch of rows x words matrices (used to stage operands).
 hipError_t launch_copy(const uint64_t* src, int64_t lds, uint64_t* dst, int64_t ldd,
@@ -124,10 +129,38 @@ struct BatchedDesc {
 // begins[i] = descs[i].tile_begin as uint32 (total tiles < 2^32); cached in LDS
 // by every workgroup when count <= kBatchedLdsProblems.
 constexpr int64_t kBatchedLdsProblems = 16384;
+// tile 1: 128 x 64 per wave, 2: 64 x 64; fmt: mfma::MfmaFormat (0 int8, 1 E2M1).
 hipError_t launch_batched_persistent(const BatchedDesc* descs, const uint32_t* begins,
                                      int64_t count, int64_t total_tiles, unsigned int* counter,
-                                     int grid, hipStream_t s);
-int batched_tile_rows();
-int batched_tile_cols();
+                                     int grid, int tile, int fmt, hipStream_t s);
+int batched_tile_rows(int tile);
+int batched_tile_cols(int tile);
+
+// Batched-plan choices recorded by the autotuner, keyed by the problem count
+// and the total work rounded to a power of two (kept with the other autotune
+// tables).
+bool batched_tuned(int64_t count, double ops, int* leaf, int* tile);
+void batched_tune_set(int64_t count, double ops, int leaf, int tile);
+
+}  // namespace bmm
+
+#include "../../include/bmm.h"
+
+namespace bmm {
+
+// Inverse of the result's basis change of a scheme (standard -> alternative basis).
+hipError_t to_alt_basis(uint64_t* C, int64_t ldc, int64_t rows, int64_t words, int depth,
+                        int scheme, hipStream_t s);
+
+// The recursion's core on operands already in the alternative basis (A, and B
+// given transposed), for callers that stage their own operands (the
+// out-of-core pipeline).  depth = -1 picks it as the public product does;
+// strassen_alt_plan reports the workspace and the depth chosen.  accumulate = 1
+// XORs the (alternative-basis) result into C.  Both return a bmm status.
+int strassen_alt_plan(int64_t m, int64_t k, int64_t n, int depth, const bmm_options& o,
+                      size_t* bytes, int* depth_out);
+int strassen_alt(const uint64_t* Ahat, int64_t lda, const uint64_t* BThat, int64_t ldbt,
+                 uint64_t* C, int64_t ldc, int64_t m, int64_t k, int64_t n, int depth,
+                 void* ws, size_t bytes, const bmm_options& o, int accumulate, hipStream_t s);
 
 }  // namespace bmm

@@ -1,19 +1,12 @@
-// Expanding and compressing levels of the alternative-basis recursion
-// (sections 3.8, 3.9, 3.11; Algorithms 1 and 2 of the paper) for the
+// Expanding and compressing levels of the recursion (sections 3.8, 3.9, 3.11;
+// Algorithms 1 and 2 of the paper) for every 2 x 2 scheme in scheme.h: the
 // self-inverse design (eqs. mb-tsrecurrence and mb-qrecurrence, matrix form
-// eq. mb-albega).
+// eq. mb-albega), the chaining design (eqs. ab-tsrecurrence and
+// ab-qrecurrence) and Strassen-Winograd (eqs. sw-input and sw-output).
 //
-// Expansion (left operand, alpha):
-//   T0 = A00, T1 = A01, T2 = A10, T3 = A11,
-//   T4 = A00 + A11, T5 = A01 + A11, T6 = A10 + A11
-// Expansion (right operand, beta):
-//   S0 = B00, S1 = B10, S2 = B00 + B11, S3 = B11,
-//   S4 = B01, S5 = B01 + B11, S6 = B10 + B11
 // The right operand is kept transposed throughout (its quadrant (j, k) lives
 // at (k, j)), so the right expansion reads the stored 01 quadrant as B10 and
 // the stored 10 quadrant as B01; each S_h is then produced already transposed.
-// Compression (gamma):
-//   C00 = Q0 + Q1, C01 = Q4 + Q6, C10 = Q2 + Q5, C11 = Q1 + Q3 + Q5 + Q6
 //
 // Every thread owns one 64-bit word position of a child (or grandchild) and
 // moves it through registers: one level reads 4 words and writes 7 (expand)
@@ -22,43 +15,15 @@
 // HBM (section 3.15, merging levels).  Children of parent p are matrices
 // 7p + h, grandchildren 49p + 7h1 + h2, stored compactly one after another.
 #include "bmm_internal.h"
+#include "scheme.h"
 
 namespace bmm {
 namespace {
 
-template <int SIDE>
-__device__ __forceinline__ void expand_one(uint64_t q00, uint64_t q01, uint64_t q10,
-                                           uint64_t q11, uint64_t (&o)[7]) {
-  if (SIDE == 0) {
-    o[0] = q00;
-    o[1] = q01;
-    o[2] = q10;
-    o[3] = q11;
-    o[4] = q00 ^ q11;
-    o[5] = q01 ^ q11;
-    o[6] = q10 ^ q11;
-  } else {
-    // stored transposed: B01 is the stored 10 quadrant, B10 the stored 01 quadrant
-    const uint64_t b00 = q00, b01 = q10, b10 = q01, b11 = q11;
-    o[0] = b00;
-    o[1] = b10;
-    o[2] = b00 ^ b11;
-    o[3] = b11;
-    o[4] = b01;
-    o[5] = b01 ^ b11;
-    o[6] = b10 ^ b11;
-  }
-}
+using scheme::compress_one;
+using scheme::expand_one;
 
-__device__ __forceinline__ void compress_one(const uint64_t (&q)[7], uint64_t& c00,
-                                             uint64_t& c01, uint64_t& c10, uint64_t& c11) {
-  c00 = q[0] ^ q[1];
-  c01 = q[4] ^ q[6];
-  c10 = q[2] ^ q[5];
-  c11 = q[1] ^ q[3] ^ q[5] ^ q[6];
-}
-
-template <int SIDE>
+template <int SCH, int SIDE>
 __global__ __launch_bounds__(256) void expand_kernel(const uint64_t* __restrict__ src,
                                                      int64_t ldp, int64_t strideP,
                                                      uint64_t* __restrict__ dst, int64_t rows,
@@ -78,14 +43,14 @@ __global__ __launch_bounds__(256) void expand_kernel(const uint64_t* __restrict_
     const uint64_t q10 = P[(r + hr) * ldp + w];
     const uint64_t q11 = P[(r + hr) * ldp + hw + w];
     uint64_t o[7];
-    expand_one<SIDE>(q00, q01, q10, q11, o);
+    expand_one<SCH, SIDE>(q00, q01, q10, q11, o);
     uint64_t* D = dst + 7 * p * csize + q;
 #pragma unroll
     for (int h = 0; h < 7; ++h) D[h * csize] = o[h];
   }
 }
 
-template <int SIDE>
+template <int SCH, int SIDE>
 __global__ __launch_bounds__(256) void expand2_kernel(const uint64_t* __restrict__ src,
                                                       int64_t ldp, int64_t strideP,
                                                       uint64_t* __restrict__ dst, int64_t rows,
@@ -118,7 +83,7 @@ __global__ __launch_bounds__(256) void expand2_kernel(const uint64_t* __restrict
 #pragma unroll
       for (int j2 = 0; j2 < 2; ++j2) {
         uint64_t o[7];
-        expand_one<SIDE>(x[0][0][i2][j2], x[0][1][i2][j2], x[1][0][i2][j2], x[1][1][i2][j2], o);
+        expand_one<SCH, SIDE>(x[0][0][i2][j2], x[0][1][i2][j2], x[1][0][i2][j2], x[1][1][i2][j2], o);
 #pragma unroll
         for (int h = 0; h < 7; ++h) t[h][i2][j2] = o[h];
       }
@@ -126,13 +91,23 @@ __global__ __launch_bounds__(256) void expand2_kernel(const uint64_t* __restrict
 #pragma unroll
     for (int h1 = 0; h1 < 7; ++h1) {
       uint64_t o[7];
-      expand_one<SIDE>(t[h1][0][0], t[h1][0][1], t[h1][1][0], t[h1][1][1], o);
+      expand_one<SCH, SIDE>(t[h1][0][0], t[h1][0][1], t[h1][1][0], t[h1][1][1], o);
 #pragma unroll
       for (int h2 = 0; h2 < 7; ++h2) D[(7 * h1 + h2) * gsize] = o[h2];
     }
   }
 }
 
+template <int ACC>
+__device__ __forceinline__ void put(uint64_t& d, uint64_t v) {
+  if (ACC)
+    d ^= v;
+  else
+    d = v;
+}
+
+// ACC = 1: the parent quadrants are XORed into dst instead of overwriting it.
+template <int SCH, int ACC>
 __global__ __launch_bounds__(256) void compress_kernel(const uint64_t* __restrict__ src,
                                                        uint64_t* __restrict__ dst, int64_t ldp,
                                                        int64_t strideP, int64_t rows,
@@ -151,15 +126,16 @@ __global__ __launch_bounds__(256) void compress_kernel(const uint64_t* __restric
 #pragma unroll
     for (int h = 0; h < 7; ++h) v[h] = S[h * csize];
     uint64_t c00, c01, c10, c11;
-    compress_one(v, c00, c01, c10, c11);
+    compress_one<SCH>(v, c00, c01, c10, c11);
     uint64_t* P = dst + p * strideP;
-    P[r * ldp + w] = c00;
-    P[r * ldp + hw + w] = c01;
-    P[(r + hr) * ldp + w] = c10;
-    P[(r + hr) * ldp + hw + w] = c11;
+    put<ACC>(P[r * ldp + w], c00);
+    put<ACC>(P[r * ldp + hw + w], c01);
+    put<ACC>(P[(r + hr) * ldp + w], c10);
+    put<ACC>(P[(r + hr) * ldp + hw + w], c11);
   }
 }
 
+template <int SCH, int ACC>
 __global__ __launch_bounds__(256) void compress2_kernel(const uint64_t* __restrict__ src,
                                                         uint64_t* __restrict__ dst, int64_t ldp,
                                                         int64_t strideP, int64_t rows,
@@ -181,7 +157,7 @@ __global__ __launch_bounds__(256) void compress2_kernel(const uint64_t* __restri
       uint64_t v[7];
 #pragma unroll
       for (int h2 = 0; h2 < 7; ++h2) v[h2] = S[(7 * h1 + h2) * gsize];
-      compress_one(v, c[h1][0][0], c[h1][0][1], c[h1][1][0], c[h1][1][1]);
+      compress_one<SCH>(v, c[h1][0][0], c[h1][0][1], c[h1][1][0], c[h1][1][1]);
     }
     uint64_t* P = dst + p * strideP + r * ldp + w;
 #pragma unroll
@@ -192,12 +168,12 @@ __global__ __launch_bounds__(256) void compress2_kernel(const uint64_t* __restri
 #pragma unroll
         for (int h1 = 0; h1 < 7; ++h1) v[h1] = c[h1][i2][k2];
         uint64_t c00, c01, c10, c11;
-        compress_one(v, c00, c01, c10, c11);
+        compress_one<SCH>(v, c00, c01, c10, c11);
         const int64_t off = i2 * qr * ldp + k2 * qw;
-        P[off] = c00;
-        P[off + 2 * qw] = c01;
-        P[off + 2 * qr * ldp] = c10;
-        P[off + 2 * qr * ldp + 2 * qw] = c11;
+        put<ACC>(P[off], c00);
+        put<ACC>(P[off + 2 * qw], c01);
+        put<ACC>(P[off + 2 * qr * ldp], c10);
+        put<ACC>(P[off + 2 * qr * ldp + 2 * qw], c11);
       }
   }
 }
@@ -232,52 +208,114 @@ inline unsigned grid_for(int64_t total) {
   return (unsigned)blocks;
 }
 
+template <int SCH>
+hipError_t expand_sch(int side, int levels, const uint64_t* src, int64_t ldp, int64_t strideP,
+                      uint64_t* dst, int64_t rows, int64_t words, int64_t parents,
+                      hipStream_t s) {
+  const int sh = levels == 2 ? 2 : 1;
+  const int64_t total = (rows >> sh) * (words >> sh) * parents;
+  if (total <= 0) return hipSuccess;
+  const dim3 g(grid_for(total)), b(256);
+  if (levels == 2) {
+    if (side == 0)
+      hipLaunchKernelGGL((expand2_kernel<SCH, 0>), g, b, 0, s, src, ldp, strideP, dst, rows,
+                         words, parents);
+    else
+      hipLaunchKernelGGL((expand2_kernel<SCH, 1>), g, b, 0, s, src, ldp, strideP, dst, rows,
+                         words, parents);
+  } else {
+    if (side == 0)
+      hipLaunchKernelGGL((expand_kernel<SCH, 0>), g, b, 0, s, src, ldp, strideP, dst, rows,
+                         words, parents);
+    else
+      hipLaunchKernelGGL((expand_kernel<SCH, 1>), g, b, 0, s, src, ldp, strideP, dst, rows,
+                         words, parents);
+  }
+  return hipGetLastError();
+}
+
+template <int SCH>
+hipError_t compress_sch(int levels, const uint64_t* src, uint64_t* dst, int64_t ldp,
+                        int64_t strideP, int64_t rows, int64_t words, int64_t parents,
+                        hipStream_t s, int accumulate) {
+  const int sh = levels == 2 ? 2 : 1;
+  const int64_t total = (rows >> sh) * (words >> sh) * parents;
+  if (total <= 0) return hipSuccess;
+  const dim3 g(grid_for(total)), b(256);
+  if (levels == 2) {
+    if (accumulate)
+      hipLaunchKernelGGL((compress2_kernel<SCH, 1>), g, b, 0, s, src, dst, ldp, strideP, rows,
+                         words, parents);
+    else
+      hipLaunchKernelGGL((compress2_kernel<SCH, 0>), g, b, 0, s, src, dst, ldp, strideP, rows,
+                         words, parents);
+  } else {
+    if (accumulate)
+      hipLaunchKernelGGL((compress_kernel<SCH, 1>), g, b, 0, s, src, dst, ldp, strideP, rows,
+                         words, parents);
+    else
+      hipLaunchKernelGGL((compress_kernel<SCH, 0>), g, b, 0, s, src, dst, ldp, strideP, rows,
+                         words, parents);
+  }
+  return hipGetLastError();
+}
+
+hipError_t expand_any(int scheme, int side, int levels, const uint64_t* src, int64_t ldp,
+                      int64_t strideP, uint64_t* dst, int64_t rows, int64_t words,
+                      int64_t parents, hipStream_t s) {
+  switch (scheme) {
+    case BMM_SCHEME_CHAINING:
+      return expand_sch<BMM_SCHEME_CHAINING>(side, levels, src, ldp, strideP, dst, rows, words,
+                                             parents, s);
+    case BMM_SCHEME_WINOGRAD:
+      return expand_sch<BMM_SCHEME_WINOGRAD>(side, levels, src, ldp, strideP, dst, rows, words,
+                                             parents, s);
+    default:
+      return expand_sch<BMM_SCHEME_SELF_INVERSE>(side, levels, src, ldp, strideP, dst, rows,
+                                                 words, parents, s);
+  }
+}
+
+hipError_t compress_any(int scheme, int levels, const uint64_t* src, uint64_t* dst, int64_t ldp,
+                        int64_t strideP, int64_t rows, int64_t words, int64_t parents,
+                        hipStream_t s, int accumulate) {
+  switch (scheme) {
+    case BMM_SCHEME_CHAINING:
+      return compress_sch<BMM_SCHEME_CHAINING>(levels, src, dst, ldp, strideP, rows, words,
+                                               parents, s, accumulate);
+    case BMM_SCHEME_WINOGRAD:
+      return compress_sch<BMM_SCHEME_WINOGRAD>(levels, src, dst, ldp, strideP, rows, words,
+                                               parents, s, accumulate);
+    default:
+      return compress_sch<BMM_SCHEME_SELF_INVERSE>(levels, src, dst, ldp, strideP, rows, words,
+                                                   parents, s, accumulate);
+  }
+}
+
 }  // namespace
 
 hipError_t launch_expand(int side, const uint64_t* src, int64_t ldp, int64_t strideP,
                          uint64_t* dst, int64_t rows, int64_t words, int64_t parents,
-                         hipStream_t s) {
-  const int64_t total = (rows >> 1) * (words >> 1) * parents;
-  if (total <= 0) return hipSuccess;
-  if (side == 0)
-    hipLaunchKernelGGL(expand_kernel<0>, dim3(grid_for(total)), dim3(256), 0, s, src, ldp,
-                       strideP, dst, rows, words, parents);
-  else
-    hipLaunchKernelGGL(expand_kernel<1>, dim3(grid_for(total)), dim3(256), 0, s, src, ldp,
-                       strideP, dst, rows, words, parents);
-  return hipGetLastError();
+                         hipStream_t s, int scheme) {
+  return expand_any(scheme, side, 1, src, ldp, strideP, dst, rows, words, parents, s);
 }
 
 hipError_t launch_expand2(int side, const uint64_t* src, int64_t ldp, int64_t strideP,
                           uint64_t* dst, int64_t rows, int64_t words, int64_t parents,
-                          hipStream_t s) {
-  const int64_t total = (rows >> 2) * (words >> 2) * parents;
-  if (total <= 0) return hipSuccess;
-  if (side == 0)
-    hipLaunchKernelGGL(expand2_kernel<0>, dim3(grid_for(total)), dim3(256), 0, s, src, ldp,
-                       strideP, dst, rows, words, parents);
-  else
-    hipLaunchKernelGGL(expand2_kernel<1>, dim3(grid_for(total)), dim3(256), 0, s, src, ldp,
-                       strideP, dst, rows, words, parents);
-  return hipGetLastError();
+                          hipStream_t s, int scheme) {
+  return expand_any(scheme, side, 2, src, ldp, strideP, dst, rows, words, parents, s);
 }
 
 hipError_t launch_compress(const uint64_t* src, uint64_t* dst, int64_t ldp, int64_t strideP,
-                           int64_t rows, int64_t words, int64_t parents, hipStream_t s) {
-  const int64_t total = (rows >> 1) * (words >> 1) * parents;
-  if (total <= 0) return hipSuccess;
-  hipLaunchKernelGGL(compress_kernel, dim3(grid_for(total)), dim3(256), 0, s, src, dst, ldp,
-                     strideP, rows, words, parents);
-  return hipGetLastError();
+                           int64_t rows, int64_t words, int64_t parents, hipStream_t s,
+                           int accumulate, int scheme) {
+  return compress_any(scheme, 1, src, dst, ldp, strideP, rows, words, parents, s, accumulate);
 }
 
 hipError_t launch_compress2(const uint64_t* src, uint64_t* dst, int64_t ldp, int64_t strideP,
-                            int64_t rows, int64_t words, int64_t parents, hipStream_t s) {
-  const int64_t total = (rows >> 2) * (words >> 2) * parents;
-  if (total <= 0) return hipSuccess;
-  hipLaunchKernelGGL(compress2_kernel, dim3(grid_for(total)), dim3(256), 0, s, src, dst, ldp,
-                     strideP, rows, words, parents);
-  return hipGetLastError();
+                            int64_t rows, int64_t words, int64_t parents, hipStream_t s,
+                            int accumulate, int scheme) {
+  return compress_any(scheme, 2, src, dst, ldp, strideP, rows, words, parents, s, accumulate);
 }
 
 hipError_t launch_copy(const uint64_t* src, int64_t lds, uint64_t* dst, int64_t ldd,

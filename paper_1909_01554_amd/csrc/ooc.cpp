@@ -50,24 +50,26 @@ struct Resources {
   hipEvent_t cdone[2] = {nullptr, nullptr}, cfree[2] = {nullptr, nullptr};
   uint64_t *a[2] = {nullptr, nullptr}, *b[2] = {nullptr, nullptr}, *c[2] = {nullptr, nullptr};
   uint64_t* bt = nullptr;
+  void* ws = nullptr;  // alternative-basis workspace (GF(2) block products)
 
   ~Resources() {
     if (copy) (void)hipStreamSynchronize(copy);
     if (comp) (void)hipStreamSynchronize(comp);
     if (down) (void)hipStreamSynchronize(down);
     for (int i = 0; i < 2; ++i) {
-      if (loaded[i]) hipEventDestroy(loaded[i]);
-      if (used[i]) hipEventDestroy(used[i]);
-      if (cdone[i]) hipEventDestroy(cdone[i]);
-      if (cfree[i]) hipEventDestroy(cfree[i]);
-      hipFree(a[i]);
-      hipFree(b[i]);
-      hipFree(c[i]);
+      if (loaded[i]) (void)hipEventDestroy(loaded[i]);
+      if (used[i]) (void)hipEventDestroy(used[i]);
+      if (cdone[i]) (void)hipEventDestroy(cdone[i]);
+      if (cfree[i]) (void)hipEventDestroy(cfree[i]);
+      (void)hipFree(a[i]);
+      (void)hipFree(b[i]);
+      (void)hipFree(c[i]);
     }
-    hipFree(bt);
-    if (copy) hipStreamDestroy(copy);
-    if (comp) hipStreamDestroy(comp);
-    if (down) hipStreamDestroy(down);
+    (void)hipFree(bt);
+    (void)hipFree(ws);
+    if (copy) (void)hipStreamDestroy(copy);
+    if (comp) (void)hipStreamDestroy(comp);
+    if (down) (void)hipStreamDestroy(down);
   }
 };
 
@@ -122,6 +124,32 @@ extern "C" int bmm_ooc(int semiring, const uint64_t* A, int64_t lda, const uint6
     return ofail(BMM_E_NOMEM, "out-of-core transpose buffer");
   }
 
+  // GF(2): the alternative-basis recursion on each block product whose shape admits
+  // it; the workspace is sized for the full block (smaller edge blocks need less).
+  const bool cubic_only = o.depth_serial == 0 && o.depth_parallel == 0;
+  size_t ws_bytes = 0;
+  if (semiring == BMM_GF2 && !cubic_only) {
+    int d = 0;
+    bmm_options po = o;
+    po.depth_serial = po.depth_parallel = -1;
+    if (strassen_alt_plan(bm, bk, bn, -1, po, &ws_bytes, &d) != BMM_OK || d == 0) {
+      ws_bytes = 0;
+    } else if (hipMalloc(&R.ws, ws_bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return ofail(BMM_E_NOMEM, "out-of-core Strassen workspace (%zu bytes)", ws_bytes);
+    }
+  }
+  // Depth of the recursion for a block product of this shape (0: cubic leaf).
+  auto block_depth = [&](int64_t r, int64_t kk, int64_t c) -> int {
+    if (!R.ws) return 0;
+    size_t need = 0;
+    int d = 0;
+    bmm_options po = o;
+    po.depth_serial = po.depth_parallel = -1;
+    if (strassen_alt_plan(r, kk, c, -1, po, &need, &d) != BMM_OK) return 0;
+    return need <= ws_bytes ? d : 0;
+  };
+
   const int64_t nI = (m + bm - 1) / bm, nJ = (k + bk - 1) / bk, nK = (n + bn - 1) / bn;
   int64_t step = 0;    // index of the (A, B) pair being staged
   int64_t cblock = 0;  // index of the C block being computed
@@ -135,6 +163,7 @@ extern "C" int bmm_ooc(int semiring, const uint64_t* A, int64_t lda, const uint6
       if (cblock >= 2) OOC_TRY(hip_ok(hipStreamWaitEvent(R.comp, R.cfree[cs], 0), "wait"));
       if (nJ == 0 || k == 0)
         OOC_TRY(hip_ok(launch_zero(R.c[cs], bnw, rows, cwords, R.comp), "zero"));
+      int cdepth = -1;  // depth of this C block's products (all J share it), -1: unset
       for (int64_t J = 0; J < nJ; ++J) {
         const int64_t depth = std::min(bk, k - J * bk);
         const int64_t dwords = (depth + 63) / 64;
@@ -153,15 +182,48 @@ extern "C" int bmm_ooc(int semiring, const uint64_t* A, int64_t lda, const uint6
         OOC_TRY(hip_ok(hipStreamWaitEvent(R.comp, R.loaded[s], 0), "wait"));
         OOC_TRY(hip_ok(launch_transpose(R.b[s], bnw, 0, R.bt, bkw, 0, depth, cols, 1, R.comp),
                        "transpose"));
-        LeafBatch p{R.a[s], bkw, 0, R.bt, bkw, 0, R.c[cs], bnw, 0, rows, depth, cols, 1,
-                    J > 0 ? 1 : 0};
-        hipError_t e = leaf == BMM_LEAF_VALU     ? launch_leaf_valu(semiring, p, tile - 1, R.comp)
-                       : leaf == BMM_LEAF_MFMA_F4 ? launch_leaf_mfma_f4(semiring, p, tile - 1, R.comp)
-                                                  : launch_leaf_mfma(semiring, p, tile - 1, R.comp);
-        OOC_TRY(hip_ok(e, "leaf"));
+        int d = block_depth(rows, depth, cols);
+        if (cdepth < 0) cdepth = d;
+        if (d != cdepth) d = 0;  // a ragged k block: cubic, in the basis the C block is in
+        if (d > 0) {
+          // A_IJ and B_JK^T change basis in their HBM slots; the product accumulates
+          // into the alternative-basis C block
+          OOC_TRY(hip_ok(launch_basis(R.a[s], bkw, 0, rows, dwords, 1, d, 0, R.comp, o.scheme, 0),
+                         "basis A"));
+          OOC_TRY(hip_ok(launch_basis(R.bt, bkw, 0, cols, dwords, 1, d, 0, R.comp, o.scheme, 1),
+                         "basis B"));
+          bmm_options po = o;
+          po.depth_serial = po.depth_parallel = -1;
+          po.leaf = leaf;
+          po.tile = o.tile;
+          OOC_TRY(strassen_alt(R.a[s], bkw, R.bt, bkw, R.c[cs], bnw, rows, depth, cols, d, R.ws,
+                               ws_bytes, po, J > 0 ? 1 : 0, R.comp));
+        } else {
+          if (cdepth > 0) {
+            // the C block is held in the alternative basis: change it to the standard
+            // basis, accumulate this product, and change it back
+            OOC_TRY(hip_ok(launch_basis(R.c[cs], bnw, 0, rows, cwords, 1, cdepth, 1, R.comp,
+                                        o.scheme, 0),
+                           "basis C"));
+          }
+          LeafBatch p{R.a[s], bkw, 0, R.bt, bkw, 0, R.c[cs], bnw, 0, rows, depth, cols, 1,
+                      J > 0 ? 1 : 0};
+          hipError_t e = leaf == BMM_LEAF_VALU ? launch_leaf_valu(semiring, p, tile - 1, R.comp)
+                         : leaf == BMM_LEAF_MFMA_F4
+                             ? launch_leaf_mfma_f4(semiring, p, tile - 1, R.comp)
+                             : launch_leaf_mfma(semiring, p, tile - 1, R.comp);
+          OOC_TRY(hip_ok(e, "leaf"));
+          if (cdepth > 0)
+            OOC_TRY(hip_ok(to_alt_basis(R.c[cs], bnw, rows, cwords, cdepth, o.scheme, R.comp),
+                           "basis C"));
+        }
         OOC_TRY(hip_ok(hipEventRecord(R.used[s], R.comp), "record"));
         ++step;
       }
+      if (cdepth > 0)
+        OOC_TRY(hip_ok(launch_basis(R.c[cs], bnw, 0, rows, cwords, 1, cdepth, 1, R.comp,
+                                    o.scheme, 0),
+                       "basis C"));
       OOC_TRY(hip_ok(hipEventRecord(R.cdone[cs], R.comp), "record"));
       OOC_TRY(hip_ok(hipStreamWaitEvent(R.down, R.cdone[cs], 0), "wait"));
       OOC_TRY(hip_ok(hipMemcpy2DAsync(C + I * bm * ldc + K * (bn / 64), ldc * 8, R.c[cs],

@@ -58,6 +58,33 @@ def test_batched_mixed(bmm, transposed):
     check(probs, host)
 
 
+@pytest.mark.parametrize("leaf", [2, 3])
+@pytest.mark.parametrize("tile", [1, 2])
+def test_batched_leaf_and_tile(bmm, leaf, tile):
+    """Every batched leaf kind (int8, fp4) and tile (128 x 64, 64 x 64)."""
+    probs, host = make_problems(36, 50 + 2 * leaf + tile)
+    announce("batched leaf/tile", leaf, tile)
+    bmm.bmm_batched(probs, options=bmm.Options(leaf=leaf, tile=tile))
+    check(probs, host)
+
+
+def test_batched_autotune_and_auto_plan(bmm):
+    probs, host = make_problems(24, 99)
+    announce("batched autotune")
+    leaf, tile, secs = bmm.bmm_autotune_batched(probs)
+    assert leaf in (2, 3) and tile in (1, 2) and secs > 0
+    check(probs, host)
+    for pr in probs:
+        pr["C"].fill_(-1)
+    plan = bmm.BatchedPlan(probs)  # AUTO: takes the recorded choice
+    plan.launch()
+    check(probs, host)
+    plan.destroy()
+    with pytest.raises(bmm.BmmError) as e:
+        bmm.bmm_batched(probs, options=bmm.Options(leaf=1))
+    assert e.value.status == -2  # no VALU batched leaf
+
+
 def test_batched_plan_graph_replay(bmm):
     import torch
     probs, host = make_problems(30, 21)
@@ -97,6 +124,31 @@ def test_ooc_small(bmm, sr):
     assert secs > 0
     got = Ch.numpy().view(np.uint64)
     assert np.array_equal(got, oracle.mul(A, B, k, n, sr))
+
+
+@pytest.mark.parametrize("cubic_only", [False, True])
+def test_ooc_gf2_alternative_basis_blocks(bmm, cubic_only):
+    """GF(2) blocks of 8192 bits run one level of the alternative-basis recursion
+    in HBM (the ragged last k block and the narrow last column block fall back to
+    the cubic leaf); sampled rows and Freivalds's check against the oracle."""
+    import torch
+    m, k, n = 16384, 16384 + 640, 16384 + 128
+    seed = 77
+    dist = bmmgen.Dist.half()
+    A = bmmgen.fill_cpu(m, k, seed, bmmgen.TAG_A, dist)
+    B = bmmgen.fill_cpu(k, n, seed, bmmgen.TAG_B, dist)
+    Ah = torch.from_numpy(A.view(np.int64)).pin_memory()
+    Bh = torch.from_numpy(B.view(np.int64)).pin_memory()
+    Ch = torch.full((m, words(n)), -1, dtype=torch.int64).pin_memory()
+    opts = bmm.Options(leaf=bmm.LEAF_MFMA_I8, depth_serial=0 if cubic_only else -1,
+                       depth_parallel=0 if cubic_only else -1)
+    announce("ooc gf2 alternative-basis blocks", cubic_only)
+    bmm.bmm_ooc(oracle.GF2, Ah, Bh, Ch, m, k, n, block=8192, options=opts)
+    got = Ch.numpy().view(np.uint64)
+    rows = bmmgen.stratified_rows(m, 64, seed)
+    assert np.array_equal(got[rows], oracle.rows(A[rows], B, k, n, oracle.GF2))
+    X = bmmgen.freivalds_vectors(m, 8, seed)
+    assert all(oracle.freivalds(A, B, got, m, k, n, X))
 
 
 def test_ooc_rejects_pageable(bmm):

@@ -35,48 +35,72 @@ def test_transpose(bmm, rows, cols):
     assert np.array_equal(got, want)
 
 
+DECS = [algebra.SELF_INVERSE, algebra.CHAINING, algebra.STRASSEN_WINOGRAD]
+
+
 @pytest.mark.parametrize("depth", [1, 2, 3, 4, 5, 6, 7])
 @pytest.mark.parametrize("inverse", [0, 1])
-def test_basis_change(bmm, depth, inverse):
+@pytest.mark.parametrize("scheme", [0, 1, 2])
+def test_basis_change(bmm, depth, inverse, scheme):
     rows, nw = 3 << depth, 2 << depth  # odd leaf rows, two-word leaf rows
     X = rand_words(rows, nw, depth)
     Xd = to_dev(X, nw + 3)
-    announce("basis", depth, inverse)
-    bmm.bmm_basis_change(Xd, rows, nw, depth, inverse=bool(inverse))
+    announce("basis", depth, inverse, scheme)
+    bmm.bmm_basis_change(Xd, rows, nw, depth, inverse=bool(inverse), scheme=scheme)
     got = from_dev(Xd, nw)
-    prog = algebra.sinv_inv if inverse else algebra.sinv_fwd
+    dec = DECS[scheme]
+    prog = dec.inv if inverse else dec.fwd
     assert np.array_equal(got, strassen.basis(X, depth, prog))
+
+
+@pytest.mark.parametrize("depth", [1, 3, 6])
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_basis_change_transposed(bmm, depth, scheme):
+    """On a right operand stored transposed, the forward change equals the
+    transpose of the change applied to the operand itself."""
+    from oracle import brute
+    rows, nw = 3 << depth, 2 << depth
+    cols = 64 * nw
+    Xs = rand_words(rows, nw, 70 + depth)  # stored: B^T, rows x cols bits
+    Xd = to_dev(Xs)
+    announce("basis transposed", depth, scheme)
+    bmm.bmm_basis_change(Xd, rows, nw, depth, scheme=scheme, transposed=True)
+    B = brute.unpack(Xs, cols).T.copy()  # cols x rows bits
+    want = brute.pack(strassen.basis(B, depth, DECS[scheme].fwd).T.copy())
+    assert np.array_equal(from_dev(Xd), want)
 
 
 @pytest.mark.parametrize("side", [0, 1])
 @pytest.mark.parametrize("levels", [1, 2])
-def test_expand(bmm, side, levels):
+@pytest.mark.parametrize("scheme", [0, 1, 2])
+def test_expand(bmm, side, levels, scheme):
     rows, nw, parents = 24, 8, 3
     X = rand_words(rows * parents, nw, 40 + side + levels)
     Xd = to_dev(X, nw + 2)  # pitch nw + 2, parents stacked with stride rows * pitch
     ch = 7 ** levels
     sub_r, sub_w = rows >> levels, nw >> levels
     Dd = empty_dev(parents * ch * sub_r, sub_w, fill=-1)
-    announce("expand", side, levels)
-    bmm.bmm_expand(side, levels, Xd, nw + 2, rows * (nw + 2), Dd, rows, nw, parents)
+    announce("expand", side, levels, scheme)
+    bmm.bmm_expand(side, levels, Xd, nw + 2, rows * (nw + 2), Dd, rows, nw, parents,
+                   scheme=scheme)
     got = from_dev(Dd).reshape(parents, ch, sub_r, sub_w)
     for p in range(parents):
         par = X[p * rows:(p + 1) * rows]
         if side == 1:
             # stored transposed: expand the real B (transpose of the stored words'
             # quadrant grid) and compare quadrant-transposed children
-            want = expand_transposed(par, levels)
+            want = expand_transposed(par, levels, DECS[scheme])
         else:
-            want = expand_plain(par, levels)
+            want = expand_plain(par, levels, DECS[scheme])
         for h in range(ch):
             assert np.array_equal(got[p, h], want[h]), (p, h)
 
 
-def expand_plain(X, levels):
-    kids = strassen.expand_left(X)
+def expand_plain(X, levels, dec):
+    kids = strassen.expand_left(X, dec)
     if levels == 1:
         return kids
-    return [g for c in kids for g in strassen.expand_left(c)]
+    return [g for c in kids for g in strassen.expand_left(c, dec)]
 
 
 def swap_quadrants(X):
@@ -84,14 +108,14 @@ def swap_quadrants(X):
     return strassen.assemble(q[0], q[2], q[1], q[3])
 
 
-def expand_transposed(X, levels):
+def expand_transposed(X, levels, dec):
     """Right-operand expansion on transposed storage at the level of quadrant
     blocks: the stored block (a, b) is B's block (b, a) transposed; children
     of the stored matrix are the stored forms of beta's children."""
     def one(Y):
         # view stored quadrants as B's quadrants: B00=Y00, B01=Y10, B10=Y01, B11=Y11
         q = strassen.quadrants(Y)
-        return [np.ascontiguousarray(t) for t in algebra.sinv_beta(q[0], q[2], q[1], q[3])]
+        return [np.ascontiguousarray(t) for t in dec.beta(q[0], q[2], q[1], q[3])]
     kids = one(X)
     if levels == 1:
         return kids
@@ -99,23 +123,26 @@ def expand_transposed(X, levels):
 
 
 @pytest.mark.parametrize("levels", [1, 2])
-def test_compress(bmm, levels):
+@pytest.mark.parametrize("scheme", [0, 1, 2])
+def test_compress(bmm, levels, scheme):
     rows, nw, parents = 16, 8, 2
     ch = 7 ** levels
     sub_r, sub_w = rows >> levels, nw >> levels
     Q = rand_words(parents * ch * sub_r, sub_w, 90 + levels)
     Qd = to_dev(Q)
     Pd = empty_dev(parents * rows, nw + 1, fill=-1)
-    announce("compress", levels)
-    bmm.bmm_compress(levels, Qd, Pd, nw + 1, rows * (nw + 1), rows, nw, parents)
+    announce("compress", levels, scheme)
+    bmm.bmm_compress(levels, Qd, Pd, nw + 1, rows * (nw + 1), rows, nw, parents, scheme=scheme)
+    dec = DECS[scheme]
     got = from_dev(Pd, nw).reshape(parents, rows, nw)
     Qs = Q.reshape(parents, ch, sub_r, sub_w)
     for p in range(parents):
         if levels == 1:
-            want = strassen.compress([Qs[p, h] for h in range(7)])
+            want = strassen.compress([Qs[p, h] for h in range(7)], dec)
         else:
-            mids = [strassen.compress([Qs[p, 7 * h1 + h2] for h2 in range(7)]) for h1 in range(7)]
-            want = strassen.compress(mids)
+            mids = [strassen.compress([Qs[p, 7 * h1 + h2] for h2 in range(7)], dec)
+                    for h1 in range(7)]
+            want = strassen.compress(mids, dec)
         assert np.array_equal(got[p], want)
 
 
@@ -147,6 +174,62 @@ def test_strassen_product(bmm, m, k, n, depth, ds, leaf):
     assert np.array_equal(from_dev(Ad), A) and np.array_equal(from_dev(Bd), B)
 
 
+SCHEME_CASES = [  # m, k, n, depth, depth_serial
+    (512, 512, 512, 1, 0), (1024, 1024, 1024, 4, 1), (2048, 2048, 2048, 5, 2),
+    (1024, 2048, 512, 2, 1), (768, 1536, 1024, 1, 1), (2048, 2048, 2048, 3, 0),
+]
+
+
+@pytest.mark.parametrize("m,k,n,depth,ds", SCHEME_CASES)
+@pytest.mark.parametrize("scheme", [1, 2])
+def test_strassen_product_schemes(bmm, m, k, n, depth, ds, scheme):
+    """The chaining alternative basis and standard-basis Strassen-Winograd reach
+    AB exactly, like the self-inverse design."""
+    import torch
+    seed = bmmgen.config_seed(2) + 3 * m + depth + scheme
+    A = bmmgen.fill_cpu(m, k, seed, bmmgen.TAG_A, bmmgen.Dist.half())
+    B = bmmgen.fill_cpu(k, n, seed, bmmgen.TAG_B, bmmgen.Dist.half())
+    opts = bmm.Options(leaf=2, depth_serial=ds, depth_parallel=depth - ds, scheme=scheme)
+    nbytes, _, _ = bmm.bmm_gf2_strassen_workspace(m, k, n, depth, opts)
+    ws = torch.empty(nbytes // 8 + 1, dtype=torch.int64, device="cuda")
+    Cd = empty_dev(m, words(n), fill=-1)
+    announce("strassen scheme", scheme, m, k, n, depth, ds)
+    bmm.bmm_gf2_strassen(to_dev(A), to_dev(B), Cd, m, k, n, ws, depth=depth, options=opts)
+    assert np.array_equal(from_dev(Cd), oracle.mul(A, B, k, n, oracle.GF2))
+
+
+@pytest.mark.parametrize("scheme", [1, 2])
+@pytest.mark.parametrize("accumulate", [False, True])
+def test_chained_products_in_alternative_basis(bmm, scheme, accumulate):
+    """Theorem 2: with the chaining design the forward and inverse changes are
+    mutual inverses, so (AB)C is computed as two alternative-basis products with
+    no change back in between (trivially so for the standard basis)."""
+    import torch
+    n, d = 1024, 3
+    mats = [bmmgen.fill_cpu(n, n, 91 + i, bmmgen.TAG_A, bmmgen.Dist.half()) for i in range(3)]
+    dev = [to_dev(x) for x in mats]
+    for x in dev:
+        bmm.bmm_basis_change(x, n, n // 64, d, scheme=scheme)
+    opts = bmm.Options(leaf=2, scheme=scheme)
+    nbytes, _, _ = bmm.bmm_gf2_strassen_workspace(n, n, n, d, opts, alt_basis_io=True)
+    ws = torch.empty(nbytes // 8 + 1, dtype=torch.int64, device="cuda")
+    P = empty_dev(n, n // 64)
+    Q = empty_dev(n, n // 64)
+    announce("chained alt-basis products", scheme, accumulate)
+    bmm.bmm_gf2_strassen(dev[0], dev[1], P, n, n, n, ws, depth=d, options=opts,
+                         alt_basis_io=True)
+    bmm.bmm_gf2_strassen(P, dev[2], Q, n, n, n, ws, depth=d, options=opts, alt_basis_io=True)
+    if accumulate:  # Q-hat ^= P-hat C-hat: a second product into the same result
+        bmm.bmm_gf2_strassen(P, dev[2], Q, n, n, n, ws, depth=d, options=opts,
+                             alt_basis_io=True, accumulate=True)
+    bmm.bmm_basis_change(Q, n, n // 64, d, inverse=True, scheme=scheme)
+    ab = oracle.mul(mats[0], mats[1], n, n, oracle.GF2)
+    want = oracle.mul(ab, mats[2], n, n, oracle.GF2)
+    if accumulate:
+        want = np.zeros_like(want)
+    assert np.array_equal(from_dev(Q), want)
+
+
 def test_strassen_alt_basis_io(bmm):
     """With A-hat, B-hat given, C-hat comes back (the core of eq. mb-mm-*)."""
     m = k = n = 1024
@@ -168,6 +251,34 @@ def test_strassen_alt_basis_io(bmm):
     # and the inverse basis change of C-hat gives AB
     assert np.array_equal(strassen.basis(want_hat, d, algebra.sinv_inv),
                           oracle.mul(A, B, k, n, oracle.GF2))
+
+
+@pytest.mark.parametrize("alt", [False, True])
+@pytest.mark.parametrize("depth,ds", [(0, 0), (1, 1), (2, 0), (3, 1)])
+@pytest.mark.parametrize("scheme", [0, 1, 2])
+def test_strassen_accumulate(bmm, alt, depth, ds, scheme):
+    """C ^= AB: in the standard basis through the inverse change's own inverse,
+    and C-hat ^= core(A-hat, B-hat) in the alternative basis."""
+    import torch
+    m, k, n = 1024, 1536, 512
+    A = bmmgen.fill_cpu(m, k, 61 + depth, bmmgen.TAG_A, bmmgen.Dist.half())
+    B = bmmgen.fill_cpu(k, n, 61 + depth, bmmgen.TAG_B, bmmgen.Dist.half())
+    C0 = bmmgen.fill_cpu(m, n, 61 + depth, 0xC, bmmgen.Dist.half())
+    dec = DECS[scheme]
+    if alt:
+        A = strassen.basis(A, depth, dec.fwd)
+        B = strassen.basis(B, depth, dec.fwd)
+        prod = strassen.core(A, B, depth, strassen.packed_leaf(k >> depth, n >> depth), dec)
+    else:
+        prod = oracle.mul(A, B, k, n, oracle.GF2)
+    opts = bmm.Options(leaf=2, depth_serial=ds, depth_parallel=depth - ds, scheme=scheme)
+    nbytes, _, _ = bmm.bmm_gf2_strassen_workspace(m, k, n, depth, opts, alt_basis_io=alt)
+    ws = torch.empty(nbytes // 8 + 1, dtype=torch.int64, device="cuda")
+    Cd = to_dev(C0, words(n) + 1)
+    announce("strassen accumulate", alt, depth, ds, scheme)
+    bmm.bmm_gf2_strassen(to_dev(A), to_dev(B), Cd, m, k, n, ws, depth=depth, options=opts,
+                         alt_basis_io=alt, accumulate=True)
+    assert np.array_equal(from_dev(Cd, words(n)), C0 ^ prod)
 
 
 def test_strassen_errors(bmm):
