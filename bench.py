@@ -24,6 +24,11 @@ PEAK_MFMA_F4_TOPS = 10100.0       # dense fp4 (E2M1) MFMA
 # 256 CU * 128 lane-ops/clk (the fp32 vector rate: 157.3 TFLOP/s / 2) * 2.4 GHz * 32 bits
 # * 2 bit operations (AND and XOR/OR) per fused v_bitop3_b32
 PEAK_VALU_FUSED_TBOPS = 5033.2
+# Bytes that one Boolean leaf launch at n = 2^18 moves between L2 and memory: rocprofv3
+# FETCH_SIZE and WRITE_SIZE of the int8 leaf with 64 x 128 tiles (the tuned tile), scaled
+# by the same counters on a 4 GiB copy in the same runs (reads x 2.0, writes x 1.0); see
+# profiles/pmc_traffic_leaf_boolean_n262144.md.  Valid for that kernel only.
+MEASURED_TRAFFIC = {("mfma", 3, 1 << 18): (8323545282.1 * 2.0 + 20985597.5) * 1024}
 
 
 def log(*a):
@@ -169,44 +174,60 @@ def run_batched(args, torch, np, bmm, bmmgen):
 
 
 def run_ooc(args, torch, np, bmm, bmmgen):
-    """GF(2) and Boolean cubic products with A, B, C in page-locked host memory,
-    streamed through HBM in blocks (double-buffered copies on their own
-    streams).  Bits: GF(2) Bernoulli(1/2), Boolean Bernoulli(2^-e) with
-    P(c = 1) ~ 0.63."""
+    """Products with A, B, C in page-locked host memory, streamed through HBM in
+    b x b blocks (copies on their own streams, overlapped with compute).  GF(2)
+    (Bernoulli(1/2) bits) with the host-level recursion and with the cubic block
+    order; Boolean (Bernoulli(2^-e), P(c = 1) ~ 0.63) in the block order.
+    Rates include every PCIe transfer."""
     import oracle
-    n = args.n
+    n, blk = args.n, min(args.block, args.n)
     nw = n // 64
     seed = bmmgen.config_seed(4)
-    out = {"mode": "ooc", "n": n, "block": args.block}
-    for name, sr, dist in [("gf2", bmm.GF2, bmmgen.Dist.half()),
-                           ("boolean", bmm.BOOLEAN,
-                            bmmgen.Dist.pow2(max(1, (n.bit_length() - 1) // 2)))]:
-        log(f"[bench] ooc {name}: generating {3 * n * nw * 8 / 2**30:.1f} GiB in pinned memory")
-        A = torch.empty((n, nw), dtype=torch.int64, pin_memory=True)
-        B = torch.empty((n, nw), dtype=torch.int64, pin_memory=True)
-        C = torch.empty((n, nw), dtype=torch.int64, pin_memory=True)
-        # generate on the GPU in row slabs and copy into the pinned buffers
-        slab = torch.empty((min(n, 1 << 15), nw), dtype=torch.int64, device="cuda")
-        for dst, tag in [(A, bmmgen.TAG_A), (B, bmmgen.TAG_B)]:
-            for r0 in range(0, n, slab.shape[0]):
-                rows = min(slab.shape[0], n - r0)
-                bmmgen.fill_tensor(slab[:rows], rows, n, seed, tag, dist, row0=r0)
-                dst[r0:r0 + rows].copy_(slab[:rows])
-        torch.cuda.synchronize()
-        secs = bmm.bmm_ooc(sr, A, B, C, n, n, n, block=args.block,
-                           options=bmm.Options(leaf=bmm.LEAF_MFMA_I8))
+    g = n // blk
+    out = {"mode": "ooc", "n": n, "block": blk}
+    log(f"[bench] ooc: {3 * n * nw * 8 / 2**30:.1f} GiB of pinned host memory")
+    A = torch.empty((n, nw), dtype=torch.int64, pin_memory=True)
+    B = torch.empty((n, nw), dtype=torch.int64, pin_memory=True)
+    C = torch.empty((n, nw), dtype=torch.int64, pin_memory=True)
+    slab = torch.empty((min(n, 1 << 15), nw), dtype=torch.int64, device="cuda")
+    block_bytes = blk * blk / 8
+    dh = g.bit_length() - 1 if g >= 2 and (g & (g - 1)) == 0 else 0
+    runs = [("gf2_host_levels", bmm.GF2, bmmgen.Dist.half(), 0),
+            ("gf2_block_order", bmm.GF2, bmmgen.Dist.half(), bmm.FLAG_OOC_BLOCK_ORDER),
+            ("boolean_block_order", bmm.BOOLEAN,
+             bmmgen.Dist.pow2(max(1, (n.bit_length() - 1) // 2)), 0)]
+    made = None
+    for name, sr, dist, flags in runs:
+        if name == "gf2_host_levels" and dh == 0:
+            continue
+        if made != (dist.kind, dist.param):
+            # generate on the GPU in row slabs and copy into the pinned buffers
+            for dst, tag in [(A, bmmgen.TAG_A), (B, bmmgen.TAG_B)]:
+                for r0 in range(0, n, slab.shape[0]):
+                    rows = min(slab.shape[0], n - r0)
+                    bmmgen.fill_tensor(slab[:rows], rows, n, seed, tag, dist, row0=r0)
+                    dst[r0:r0 + rows].copy_(slab[:rows])
+            torch.cuda.synchronize()
+            made = (dist.kind, dist.param)
+        log(f"[bench] ooc {name}")
+        secs = bmm.bmm_ooc(sr, A, B, C, n, n, n, block=blk,
+                           options=bmm.Options(leaf=bmm.LEAF_MFMA_I8, flags=flags))
         rows = bmmgen.stratified_rows(n, 16, seed)
         Ar = bmmgen.fill_rows_cpu(rows, n, seed, bmmgen.TAG_A, dist)
-        Bh = B.numpy().view(np.uint64)
-        want = oracle.rows(Ar, Bh, n, n, sr)
+        want = oracle.rows(Ar, B.numpy().view(np.uint64), n, n, sr)
         got = C[rows].numpy().view(np.uint64)
-        blocks = (n + args.block - 1) // args.block
-        h2d = blocks ** 3 * 2 * min(args.block, n) ** 2 / 8
+        if name == "gf2_host_levels":  # 14 blocks of A and 14 of B per level and instance
+            h2d = 2 * 14 ** dh * block_bytes
+            d2h = n * n / 8
+        else:
+            h2d = 2 * g ** 3 * block_bytes
+            d2h = n * n / 8
         out[name] = {"seconds": round(secs, 3), "pbops": round(2.0 * n ** 3 / secs / 1e15, 4),
-                     "h2d_bytes": h2d, "pcie_inclusive_h2d_gbs": round(h2d / secs / 1e9, 2),
+                     "h2d_bytes": h2d, "d2h_bytes": d2h,
+                     "pcie_gbs": round((h2d + d2h) / secs / 1e9, 2),
                      "verified_rows": len(rows), "verified": bool(np.array_equal(got, want))}
         log(f"[bench] ooc {name}: {secs:.2f} s {out[name]}")
-        del A, B, C, slab
+    del A, B, C, slab
     print(json.dumps(out), flush=True)
 
 
@@ -457,6 +478,8 @@ def main():
 
     value = 2 * bops / step_s / 1e15
     achieved = bops / leaf_s / 1e12  # TOP/s of the Boolean leaf launch
+    _, leaf_tile = bmm.bmm_leaf_choice(bmm.BOOLEAN, n, n, n, 1, opts(LEAF[args.leaf]))
+    traffic = MEASURED_TRAFFIC.get((args.leaf, leaf_tile, n))
     peak = {"mfma": PEAK_MFMA_I8_TOPS, "f4": PEAK_MFMA_F4_TOPS,
             "valu": PEAK_VALU_FUSED_TBOPS}[args.leaf]
     line = {
@@ -486,10 +509,10 @@ def main():
         "gf2_schemes": schemes,
         "roofline": {"bound": "alu" if args.leaf == "valu" else "mfma",
                      "kernel": ("leaf_valu_kernel" if args.leaf == "valu" else "leaf_mfma_kernel")
-                               + " (Boolean cubic product, one launch per step)",
+                               + f" tile {leaf_tile} (Boolean cubic product, one launch per step)",
                      "achieved": round(achieved, 1), "peak": peak,
                      "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-                     "traffic": None},
+                     "traffic": traffic},
         "cpu_baseline": cpu,
         "verified": verified,
     }

@@ -82,6 +82,8 @@ typedef enum {
                                        paper's timing convention, section 4.2) */
 #define BMM_FLAG_HOST_OPERANDS 0x8u /* A, B, C are page-locked host memory; blocks
                                        stream through HBM (out-of-core pipeline) */
+#define BMM_FLAG_OOC_BLOCK_ORDER 0x10u /* out-of-core GF(2): stream the cubic block
+                                          order instead of the host-level recursion */
 
 typedef struct {
   int leaf;           /* bmm_leaf; 0 = auto */
@@ -231,6 +233,11 @@ int bmm_compress(int levels, int scheme, const uint64_t* src, uint64_t* dst, int
  * 1..count; 0 = auto), and the C tile (rows x columns) of a variant. */
 int bmm_leaf_tiles(int leaf, int* count_out);
 int bmm_leaf_tile_shape(int leaf, int tile, int* rows_out, int* cols_out);
+/* The leaf kind and tile a cubic product (batch = 1) or a batch of equal leaf
+ * products of this shape would run with these options (the autotune table's
+ * entry, else the default rule); no device work. */
+int bmm_leaf_choice(int semiring, int64_t m, int64_t k, int64_t n, int64_t batch,
+                    const bmm_options* opt, int* leaf_out, int* tile_out);
 
 /* Autotuner (the paper fixes its layer depths empirically under memory limits,
  * section 3.17).  Leaf table: bmm_autotune_leaf times every leaf kernel and tile

@@ -18,12 +18,13 @@ __all__ = [
     "BmmError", "Options", "GF2", "BOOLEAN", "LEAF_AUTO", "LEAF_VALU", "LEAF_MFMA_I8",
     "LEAF_MFMA_F4",
     "FLAG_ACCUMULATE", "FLAG_B_TRANSPOSED", "FLAG_ALT_BASIS_IO", "FLAG_HOST_OPERANDS",
+    "FLAG_OOC_BLOCK_ORDER",
     "SCHEME_SELF_INVERSE", "SCHEME_CHAINING", "SCHEME_WINOGRAD",
     "words", "bmm_gf2", "bmm_boolean", "bmm_gf2_strassen", "bmm_gf2_strassen_workspace",
     "bmm_batched", "BatchedPlan", "bmm_transpose", "bmm_basis_change", "bmm_expand",
     "bmm_compress", "bmm_ooc", "bmm_autotune_cubic", "bmm_autotune_leaf",
     "bmm_autotune_strassen", "bmm_autotune_set", "bmm_autotune_batched", "bmm_autotune_save",
-    "bmm_autotune_load", "bmm_leaf_tiles", "bmm_leaf_tile_shape", "bmm_version",
+    "bmm_autotune_load", "bmm_leaf_tiles", "bmm_leaf_tile_shape", "bmm_leaf_choice", "bmm_version",
     "bmm_finalize", "library_path",
 ]
 
@@ -33,6 +34,7 @@ FLAG_ACCUMULATE = 0x1
 FLAG_B_TRANSPOSED = 0x2
 FLAG_ALT_BASIS_IO = 0x4
 FLAG_HOST_OPERANDS = 0x8
+FLAG_OOC_BLOCK_ORDER = 0x10
 SCHEME_SELF_INVERSE, SCHEME_CHAINING, SCHEME_WINOGRAD = 0, 1, 2
 
 _STATUS = {0: "ok", -1: "invalid argument", -2: "unsupported", -3: "workspace too small",
@@ -93,6 +95,8 @@ _c_strassen_ws = _sig("bmm_gf2_strassen_workspace",
                        ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(_int),
                        ctypes.POINTER(_int)])
 _c_batched = _sig("bmm_batched", [ctypes.POINTER(Problem), _i64, ctypes.POINTER(Options), _vp])
+_c_leaf_choice = _sig("bmm_leaf_choice", [_int, _i64, _i64, _i64, _i64, ctypes.POINTER(Options),
+                                          ctypes.POINTER(_int), ctypes.POINTER(_int)])
 _c_tune_batched = _sig("bmm_autotune_batched", [ctypes.POINTER(Problem), _i64,
                                                 ctypes.POINTER(_int), ctypes.POINTER(_int),
                                                 ctypes.POINTER(ctypes.c_double)])
@@ -359,6 +363,16 @@ def bmm_leaf_tiles(leaf):
     c = _int(0)
     _check(_c_tiles(leaf, ctypes.byref(c)))
     return c.value
+
+
+def bmm_leaf_choice(semiring, m, k, n, batch=1, options=None):
+    """(leaf, tile) that a product of this shape would run with these options."""
+    o = _opts(options, 0)
+    leaf = _int(0)
+    tile = _int(0)
+    _check(_c_leaf_choice(semiring, m, k, n, batch, ctypes.byref(o), ctypes.byref(leaf),
+                          ctypes.byref(tile)))
+    return leaf.value, tile.value
 
 
 def bmm_leaf_tile_shape(leaf, tile):

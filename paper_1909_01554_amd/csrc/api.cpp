@@ -666,6 +666,15 @@ int bmm_leaf_tiles(int leaf, int* count_out) {
   return BMM_OK;
 }
 
+int bmm_leaf_choice(int semiring, int64_t m, int64_t k, int64_t n, int64_t batch,
+                    const bmm_options* opt, int* leaf_out, int* tile_out) {
+  if (semiring != BMM_GF2 && semiring != BMM_BOOLEAN) return fail(BMM_E_INVAL, "bad semiring");
+  if (m < 0 || k < 0 || n < 0 || batch <= 0) return fail(BMM_E_INVAL, "bad shape");
+  if (!leaf_out || !tile_out) return fail(BMM_E_INVAL, "null output");
+  pick_leaf(semiring, m, k, n, batch, opt ? *opt : defaults(), leaf_out, tile_out);
+  return BMM_OK;
+}
+
 int bmm_leaf_tile_shape(int leaf, int tile, int* rows_out, int* cols_out) {
   if (!rows_out || !cols_out) return fail(BMM_E_INVAL, "null output");
   if (leaf == BMM_LEAF_VALU && tile == 1) {

@@ -190,6 +190,18 @@ __global__ __launch_bounds__(256) void copy_kernel(const uint64_t* __restrict__ 
   }
 }
 
+__global__ __launch_bounds__(256) void xor_kernel(const uint64_t* __restrict__ src, int64_t lds,
+                                                  uint64_t* __restrict__ dst, int64_t ldd,
+                                                  int64_t rows, int64_t words) {
+  const int64_t total = rows * words;
+  const int64_t gstride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gstride) {
+    const int64_t r = e / words;
+    const int64_t w = e - r * words;
+    dst[r * ldd + w] ^= src[r * lds + w];
+  }
+}
+
 __global__ __launch_bounds__(256) void zero_kernel(uint64_t* __restrict__ dst, int64_t ld,
                                                    int64_t rows, int64_t words) {
   const int64_t total = rows * words;
@@ -324,6 +336,15 @@ hipError_t launch_copy(const uint64_t* src, int64_t lds, uint64_t* dst, int64_t 
   if (total <= 0) return hipSuccess;
   hipLaunchKernelGGL(copy_kernel, dim3(grid_for(total)), dim3(256), 0, s, src, lds, dst, ldd,
                      rows, words);
+  return hipGetLastError();
+}
+
+hipError_t launch_xor(const uint64_t* src, int64_t lds, uint64_t* dst, int64_t ldd, int64_t rows,
+                      int64_t words, hipStream_t s) {
+  const int64_t total = rows * words;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(xor_kernel, dim3(grid_for(total)), dim3(256), 0, s, src, lds, dst, ldd, rows,
+                     words);
   return hipGetLastError();
 }
 

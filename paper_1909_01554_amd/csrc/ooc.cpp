@@ -1,6 +1,16 @@
 // Out-of-core product on one GPU (sections 3.3, 3.16 and 3.18 of the paper,
 // re-planned for a single device with large HBM).
 //
+// GF(2) with square operands of 2^dh blocks per side runs dh host levels of the
+// recursion (sections 3.7 and 3.12, Algorithm 3): for each of the 7^dh
+// sub-instances the GPU forms its two operands from uploaded standard-basis
+// blocks (the weights of alpha.phi and beta.phi, e.g. 14 blocks of A per level
+// for the self-inverse design), changes them to the device levels' basis,
+// runs the recursion's core, and XORs the product into its gamma targets in an
+// HBM copy of C-hat; one inverse basis change over all dh + d levels finishes
+// C before a single download.  This does (7/8)^dh of the block-order work.
+// Other shapes, and GF(2) with BMM_FLAG_OOC_BLOCK_ORDER, use the block order:
+//
 // A, B and C live in page-locked host memory.  C is cut into b x b blocks;
 // for each block (I, K) the pipeline streams the pairs (A_IJ, B_JK) through two
 // HBM slots: a copy stream uploads the next pair while the compute stream
@@ -17,6 +27,7 @@
 
 #include "../../include/bmm.h"
 #include "bmm_internal.h"
+#include "scheme.h"
 
 using namespace bmm;
 
@@ -73,6 +84,197 @@ struct Resources {
   }
 };
 
+// Coefficient masks of one host level of a scheme: a[h] and b[h] over the
+// standard quadrants (bit q, order 00 01 10 11) of A and B for operand h, and
+// g[q] over the seven products for result quadrant q, from the scheme's own
+// programs run on masks.
+struct LevelMasks {
+  uint32_t a[7], b[7], g[4];
+};
+
+template <int SCH>
+LevelMasks level_masks() {
+  LevelMasks L;
+  uint64_t o[7];
+  uint64_t x00 = 1, x01 = 2, x10 = 4, x11 = 8;
+  scheme::fwd<SCH>(x00, x01, x10, x11);
+  scheme::alpha<SCH>(x00, x01, x10, x11, o);
+  for (int h = 0; h < 7; ++h) L.a[h] = (uint32_t)o[h];
+  uint64_t y00 = 1, y01 = 2, y10 = 4, y11 = 8;
+  scheme::fwd<SCH>(y00, y01, y10, y11);
+  scheme::beta<SCH>(y00, y01, y10, y11, o);
+  for (int h = 0; h < 7; ++h) L.b[h] = (uint32_t)o[h];
+  uint64_t q[7];
+  for (int h = 0; h < 7; ++h) q[h] = 1ull << h;
+  uint64_t c[4];
+  scheme::compress_one<SCH>(q, c[0], c[1], c[2], c[3]);
+  for (int i = 0; i < 4; ++i) L.g[i] = (uint32_t)c[i];
+  return L;
+}
+
+LevelMasks masks_of(int sch) {
+  if (sch == BMM_SCHEME_CHAINING) return level_masks<BMM_SCHEME_CHAINING>();
+  if (sch == BMM_SCHEME_WINOGRAD) return level_masks<BMM_SCHEME_WINOGRAD>();
+  return level_masks<BMM_SCHEME_SELF_INVERSE>();
+}
+
+// Quadrant of block (r, c) of a 2^dh x 2^dh grid at host level l (0 = top).
+inline int quad_at(int64_t r, int64_t c, int dh, int l) {
+  const int sh = dh - 1 - l;
+  return (int)(((r >> sh) & 1) << 1 | ((c >> sh) & 1));
+}
+
+// Digit of sub-instance h at host level l (base 7, top level most significant).
+inline int digit_at(int64_t h, int dh, int l) {
+  for (int i = dh - 1; i > l; --i) h /= 7;
+  return (int)(h % 7);
+}
+
+struct HostRes {
+  hipStream_t copy = nullptr, comb = nullptr, comp = nullptr;
+  hipEvent_t loaded[2] = {}, freed[2] = {}, ready[2] = {}, done[2] = {};
+  uint64_t *stage[2] = {}, *T[2] = {}, *ST[2] = {}, *btmp = nullptr, *Q = nullptr,
+           *Chat = nullptr;
+  void* ws = nullptr;
+
+  ~HostRes() {
+    for (hipStream_t st : {copy, comb, comp})
+      if (st) (void)hipStreamSynchronize(st);
+    for (int i = 0; i < 2; ++i) {
+      for (hipEvent_t e : {loaded[i], freed[i], ready[i], done[i]})
+        if (e) (void)hipEventDestroy(e);
+      (void)hipFree(stage[i]);
+      (void)hipFree(T[i]);
+      (void)hipFree(ST[i]);
+    }
+    (void)hipFree(btmp);
+    (void)hipFree(Q);
+    (void)hipFree(Chat);
+    (void)hipFree(ws);
+    for (hipStream_t st : {copy, comb, comp})
+      if (st) (void)hipStreamDestroy(st);
+  }
+};
+
+// The host-level recursion; returns 1 (nothing done) when the shape or the free
+// HBM does not admit it, else a bmm status.
+int ooc_host_levels(const uint64_t* A, int64_t lda, const uint64_t* B, int64_t ldb,
+                    uint64_t* C, int64_t ldc, int64_t n, int64_t b, const bmm_options& o,
+                    int leaf) {
+  if (n % b || n / b < 2 || b % 64) return 1;
+  int dh = 0;
+  while (((int64_t)b << dh) < n) ++dh;
+  if (((int64_t)b << dh) != n) return 1;  // n / b must be a power of two
+  bmm_options po = o;
+  po.depth_serial = po.depth_parallel = -1;
+  po.leaf = leaf;
+  po.flags = 0;
+  size_t ws_bytes = 0;
+  int d = 0;
+  if (strassen_alt_plan(b, b, b, -1, po, &ws_bytes, &d) != BMM_OK) return 1;
+  const int64_t bw = b / 64, nw = n / 64;
+  const size_t blk = (size_t)b * bw * 8;
+  const size_t need = 8 * blk + (size_t)n * nw * 8 + ws_bytes;
+  size_t free_b = 0, total_b = 0;
+  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+    (void)hipGetLastError();
+    return 1;
+  }
+  if (need + ((size_t)1 << 30) > free_b) return 1;
+
+  const LevelMasks L = masks_of(o.scheme);
+  const int64_t g = (int64_t)1 << dh;  // blocks per side
+  int64_t H = 1;
+  for (int l = 0; l < dh; ++l) H *= 7;
+  auto coef = [&](const uint32_t* m, int64_t h, int64_t r, int64_t c) {
+    for (int l = 0; l < dh; ++l)
+      if (!((m[digit_at(h, dh, l)] >> quad_at(r, c, dh, l)) & 1)) return false;
+    return true;
+  };
+  auto coef_c = [&](int64_t h, int64_t r, int64_t c) {
+    for (int l = 0; l < dh; ++l)
+      if (!((L.g[quad_at(r, c, dh, l)] >> digit_at(h, dh, l)) & 1)) return false;
+    return true;
+  };
+
+  HostRes R;
+  for (hipStream_t* st : {&R.copy, &R.comb, &R.comp})
+    OOC_TRY(hip_ok(hipStreamCreateWithFlags(st, hipStreamNonBlocking), "stream"));
+  for (int i = 0; i < 2; ++i) {
+    for (hipEvent_t* e : {&R.loaded[i], &R.freed[i], &R.ready[i], &R.done[i]})
+      OOC_TRY(hip_ok(hipEventCreateWithFlags(e, hipEventDisableTiming), "event"));
+    if (hipMalloc((void**)&R.stage[i], blk) != hipSuccess ||
+        hipMalloc((void**)&R.T[i], blk) != hipSuccess ||
+        hipMalloc((void**)&R.ST[i], blk) != hipSuccess) {
+      (void)hipGetLastError();
+      return ofail(BMM_E_NOMEM, "out-of-core host-level buffers");
+    }
+  }
+  if (hipMalloc((void**)&R.btmp, blk) != hipSuccess || hipMalloc((void**)&R.Q, blk) != hipSuccess ||
+      hipMalloc((void**)&R.Chat, (size_t)n * nw * 8) != hipSuccess ||
+      (ws_bytes && hipMalloc(&R.ws, ws_bytes) != hipSuccess)) {
+    (void)hipGetLastError();
+    return ofail(BMM_E_NOMEM, "out-of-core host-level buffers");
+  }
+  OOC_TRY(hip_ok(launch_zero(R.Chat, nw, n, nw, R.comp), "zero C"));
+
+  int64_t up = 0;  // blocks uploaded so far (staging slot up % 2)
+  for (int64_t h = 0; h < H; ++h) {
+    const int t = (int)(h & 1);
+    if (h >= 2) OOC_TRY(hip_ok(hipStreamWaitEvent(R.comb, R.done[t], 0), "wait"));
+    for (int side = 0; side < 2; ++side) {
+      bool first = true;
+      for (int64_t r = 0; r < g; ++r)
+        for (int64_t c = 0; c < g; ++c) {
+          if (!coef(side == 0 ? L.a : L.b, h, r, c)) continue;
+          const int s = (int)(up & 1);
+          if (up >= 2) OOC_TRY(hip_ok(hipStreamWaitEvent(R.copy, R.freed[s], 0), "wait"));
+          const uint64_t* src = side == 0 ? A + r * b * lda + c * bw : B + r * b * ldb + c * bw;
+          const int64_t ld = side == 0 ? lda : ldb;
+          OOC_TRY(hip_ok(hipMemcpy2DAsync(R.stage[s], bw * 8, src, ld * 8, bw * 8, b,
+                                          hipMemcpyHostToDevice, R.copy),
+                         "H2D block"));
+          OOC_TRY(hip_ok(hipEventRecord(R.loaded[s], R.copy), "record"));
+          OOC_TRY(hip_ok(hipStreamWaitEvent(R.comb, R.loaded[s], 0), "wait"));
+          const uint64_t* add = R.stage[s];
+          uint64_t* acc = side == 0 ? R.T[t] : R.ST[t];
+          if (side == 1) {  // B block (J, K) -> its transpose, stored as block (K, J) of B^T
+            OOC_TRY(hip_ok(launch_transpose(R.stage[s], bw, 0, R.btmp, bw, 0, b, b, 1, R.comb),
+                           "transpose"));
+            add = R.btmp;
+          }
+          OOC_TRY(hip_ok(first ? launch_copy(add, bw, acc, bw, b, bw, R.comb)
+                               : launch_xor(add, bw, acc, bw, b, bw, R.comb),
+                         "combine"));
+          OOC_TRY(hip_ok(hipEventRecord(R.freed[s], R.comb), "record"));
+          first = false;
+          ++up;
+        }
+      if (first) OOC_TRY(hip_ok(launch_zero(side == 0 ? R.T[t] : R.ST[t], bw, b, bw, R.comb),
+                                "zero"));
+    }
+    OOC_TRY(hip_ok(launch_basis(R.T[t], bw, 0, b, bw, 1, d, 0, R.comb, o.scheme, 0), "basis"));
+    OOC_TRY(hip_ok(launch_basis(R.ST[t], bw, 0, b, bw, 1, d, 0, R.comb, o.scheme, 1), "basis"));
+    OOC_TRY(hip_ok(hipEventRecord(R.ready[t], R.comb), "record"));
+    OOC_TRY(hip_ok(hipStreamWaitEvent(R.comp, R.ready[t], 0), "wait"));
+    OOC_TRY(strassen_alt(R.T[t], bw, R.ST[t], bw, R.Q, bw, b, b, b, d, R.ws, ws_bytes, po, 0,
+                         R.comp));
+    OOC_TRY(hip_ok(hipEventRecord(R.done[t], R.comp), "record"));
+    for (int64_t r = 0; r < g; ++r)
+      for (int64_t c = 0; c < g; ++c)
+        if (coef_c(h, r, c))
+          OOC_TRY(hip_ok(launch_xor(R.Q, bw, R.Chat + r * b * nw + c * bw, nw, b, bw, R.comp),
+                         "accumulate"));
+  }
+  OOC_TRY(hip_ok(launch_basis(R.Chat, nw, 0, n, nw, 1, dh + d, 1, R.comp, o.scheme, 0),
+                 "basis C"));
+  OOC_TRY(hip_ok(hipMemcpy2DAsync(C, ldc * 8, R.Chat, nw * 8, nw * 8, n, hipMemcpyDeviceToHost,
+                                  R.comp),
+                 "D2H C"));
+  OOC_TRY(hip_ok(hipStreamSynchronize(R.comp), "sync"));
+  return BMM_OK;
+}
+
 }  // namespace
 
 extern "C" int bmm_ooc(int semiring, const uint64_t* A, int64_t lda, const uint64_t* B,
@@ -103,6 +305,16 @@ extern "C" int bmm_ooc(int semiring, const uint64_t* A, int64_t lda, const uint6
   int tile = o.tile > 0 ? o.tile : 1;
 
   const auto t0 = std::chrono::steady_clock::now();
+  if (semiring == BMM_GF2 && !(o.flags & BMM_FLAG_OOC_BLOCK_ORDER) &&
+      !(o.depth_serial == 0 && o.depth_parallel == 0) && m == k && k == n) {
+    const int rc = ooc_host_levels(A, lda, B, ldb, C, ldc, n, block, o, leaf);
+    if (rc != 1) {
+      if (rc == BMM_OK && seconds_out)
+        *seconds_out =
+            std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      return rc;
+    }
+  }
   Resources R;
   OOC_TRY(hip_ok(hipStreamCreateWithFlags(&R.copy, hipStreamNonBlocking), "stream"));
   OOC_TRY(hip_ok(hipStreamCreateWithFlags(&R.comp, hipStreamNonBlocking), "stream"));

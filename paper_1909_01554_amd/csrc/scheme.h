@@ -13,6 +13,10 @@
 //   WINOGRAD (section 2.1, the standard basis):
 //     no basis change; eqs. sw-input and sw-output
 //
+// The programs also run on the host: fed the masks 1, 2, 4, 8 for the four
+// quadrants (1 << h for the seven products) they return, as bit masks, the
+// coefficient sets of their outputs, which the out-of-core host levels use.
+//
 // The same forward change applies to both operands.  The right operand is
 // kept transposed (its quadrant (j, k) stored at (k, j)), so on it the
 // programs read the stored 01 quadrant as B10 and the stored 10 as B01.
@@ -27,7 +31,8 @@ namespace scheme {
 
 // Forward basis change of one 2x2 block (in place).
 template <int SCH>
-__device__ __forceinline__ void fwd(uint64_t& x00, uint64_t& x01, uint64_t& x10, uint64_t& x11) {
+__host__ __device__ __forceinline__ void fwd(uint64_t& x00, uint64_t& x01, uint64_t& x10,
+                                             uint64_t& x11) {
   (void)x00;
   if constexpr (SCH == BMM_SCHEME_SELF_INVERSE) {
     x11 ^= x01 ^ x10;
@@ -39,7 +44,8 @@ __device__ __forceinline__ void fwd(uint64_t& x00, uint64_t& x01, uint64_t& x10,
 
 // Inverse basis change of the result (in place).
 template <int SCH>
-__device__ __forceinline__ void inv(uint64_t& x00, uint64_t& x01, uint64_t& x10, uint64_t& x11) {
+__host__ __device__ __forceinline__ void inv(uint64_t& x00, uint64_t& x01, uint64_t& x10,
+                                             uint64_t& x11) {
   (void)x00;
   if constexpr (SCH == BMM_SCHEME_SELF_INVERSE) {
     x01 ^= x11;
@@ -62,8 +68,8 @@ constexpr int written() {
 
 // Left operand (alpha): seven children from A's quadrants.
 template <int SCH>
-__device__ __forceinline__ void alpha(uint64_t a00, uint64_t a01, uint64_t a10, uint64_t a11,
-                                      uint64_t (&o)[7]) {
+__host__ __device__ __forceinline__ void alpha(uint64_t a00, uint64_t a01, uint64_t a10,
+                                               uint64_t a11, uint64_t (&o)[7]) {
   if constexpr (SCH == BMM_SCHEME_SELF_INVERSE) {
     o[0] = a00;
     o[1] = a01;
@@ -96,8 +102,8 @@ __device__ __forceinline__ void alpha(uint64_t a00, uint64_t a01, uint64_t a10, 
 
 // Right operand (beta), from B's quadrants in the standard orientation.
 template <int SCH>
-__device__ __forceinline__ void beta(uint64_t b00, uint64_t b01, uint64_t b10, uint64_t b11,
-                                     uint64_t (&o)[7]) {
+__host__ __device__ __forceinline__ void beta(uint64_t b00, uint64_t b01, uint64_t b10,
+                                              uint64_t b11, uint64_t (&o)[7]) {
   if constexpr (SCH == BMM_SCHEME_SELF_INVERSE) {
     o[0] = b00;
     o[1] = b10;
@@ -130,8 +136,8 @@ __device__ __forceinline__ void beta(uint64_t b00, uint64_t b01, uint64_t b10, u
 
 // Expansion of a stored operand: SIDE 0 = left (alpha), 1 = right stored transposed (beta).
 template <int SCH, int SIDE>
-__device__ __forceinline__ void expand_one(uint64_t q00, uint64_t q01, uint64_t q10,
-                                           uint64_t q11, uint64_t (&o)[7]) {
+__host__ __device__ __forceinline__ void expand_one(uint64_t q00, uint64_t q01, uint64_t q10,
+                                                    uint64_t q11, uint64_t (&o)[7]) {
   if constexpr (SIDE == 0)
     alpha<SCH>(q00, q01, q10, q11, o);
   else
@@ -140,8 +146,9 @@ __device__ __forceinline__ void expand_one(uint64_t q00, uint64_t q01, uint64_t 
 
 // Combination of the seven products into the four result quadrants (gamma / zeta).
 template <int SCH>
-__device__ __forceinline__ void compress_one(const uint64_t (&q)[7], uint64_t& c00,
-                                             uint64_t& c01, uint64_t& c10, uint64_t& c11) {
+__host__ __device__ __forceinline__ void compress_one(const uint64_t (&q)[7], uint64_t& c00,
+                                                      uint64_t& c01, uint64_t& c10,
+                                                      uint64_t& c11) {
   if constexpr (SCH == BMM_SCHEME_SELF_INVERSE) {
     c00 = q[0] ^ q[1];
     c01 = q[4] ^ q[6];

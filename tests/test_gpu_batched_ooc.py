@@ -151,6 +151,35 @@ def test_ooc_gf2_alternative_basis_blocks(bmm, cubic_only):
     assert all(oracle.freivalds(A, B, got, m, k, n, X))
 
 
+@pytest.mark.parametrize("scheme", [0, 1, 2])
+@pytest.mark.parametrize("dh", [1, 2])
+@pytest.mark.parametrize("block_order", [False, True])
+def test_ooc_gf2_host_levels(bmm, scheme, dh, block_order):
+    """Square GF(2) operands of 2^dh blocks per side: dh host levels of the
+    recursion (7^dh sub-instances formed on the GPU from uploaded blocks, one
+    device level each), or the cubic block order; sampled rows and Freivalds's
+    check against the oracle."""
+    import torch
+    blk = 8192
+    n = blk << dh
+    seed = 300 + 10 * scheme + dh
+    dist = bmmgen.Dist.half()
+    A = bmmgen.fill_cpu(n, n, seed, bmmgen.TAG_A, dist)
+    B = bmmgen.fill_cpu(n, n, seed, bmmgen.TAG_B, dist)
+    Ah = torch.from_numpy(A.view(np.int64)).pin_memory()
+    Bh = torch.from_numpy(B.view(np.int64)).pin_memory()
+    Ch = torch.full((n, words(n)), -1, dtype=torch.int64).pin_memory()
+    opts = bmm.Options(leaf=bmm.LEAF_MFMA_I8, scheme=scheme,
+                       flags=bmm.FLAG_OOC_BLOCK_ORDER if block_order else 0)
+    announce("ooc gf2 host levels", scheme, dh, block_order)
+    bmm.bmm_ooc(oracle.GF2, Ah, Bh, Ch, n, n, n, block=blk, options=opts)
+    got = Ch.numpy().view(np.uint64)
+    rows = bmmgen.stratified_rows(n, 64, seed)
+    assert np.array_equal(got[rows], oracle.rows(A[rows], B, n, n, oracle.GF2))
+    X = bmmgen.freivalds_vectors(n, 8, seed)
+    assert all(oracle.freivalds(A, B, got, n, n, n, X))
+
+
 def test_ooc_rejects_pageable(bmm):
     A = np.zeros((64, 1), np.uint64)
     with pytest.raises(bmm.BmmError) as e:
