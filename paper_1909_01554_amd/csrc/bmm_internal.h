@@ -62,16 +62,13 @@ __device__ __forceinline__ TileCoord xcd_tile(int64_t g, int64_t total, int64_t 
 
 // MFMA leaf variants (rows x cols of C per wave).
 enum MfmaTile { MFMA_128x64 = 0, MFMA_64x64 = 1, MFMA_64x128 = 2, MFMA_64x32 = 3,
-                MFMA_LDS_256x256 = 4, MFMA_P_128x64 = 5, MFMA_P_64x128 = 6, MFMA_NUM_TILES };
+                MFMA_LDS_256x256 = 4, MFMA_NUM_TILES };
 
 hipError_t launch_leaf_mfma(int semiring, const LeafBatch& p, int tile, hipStream_t s);
 // The same tiles on E2M1 (fp4) operands with exact fp32 sums; requires k < 2^24.
 hipError_t launch_leaf_mfma_f4(int semiring, const LeafBatch& p, int tile, hipStream_t s);
 // The 8-wave workgroup variant that shares operand panels through LDS (fmt 0: int8, 1: fp4).
 hipError_t launch_leaf_mfma_lds(int semiring, int fmt, const LeafBatch& p, hipStream_t s);
-// Persistent workgroups that prefetch across tiles (tile MFMA_P_128x64 or MFMA_P_64x128).
-hipError_t launch_leaf_mfma_persist(int semiring, int fmt, const LeafBatch& p, int tile,
-                                    hipStream_t s);
 hipError_t launch_leaf_valu(int semiring, const LeafBatch& p, int tile, hipStream_t s);
 int leaf_mfma_tile_rows(int tile);
 int leaf_mfma_tile_cols(int tile);

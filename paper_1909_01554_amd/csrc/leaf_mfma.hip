@@ -64,8 +64,6 @@ template <int SEMI, int FMT>
 hipError_t launch_semi(const LeafBatch& p, int tile, hipStream_t s) {
   switch (tile) {
     case MFMA_LDS_256x256: return launch_leaf_mfma_lds(SEMI, FMT, p, s);
-    case MFMA_P_128x64:
-    case MFMA_P_64x128: return launch_leaf_mfma_persist(SEMI, FMT, p, tile, s);
     case MFMA_64x64: return launch_t<SEMI, 2, 2, FMT>(p, s);
     case MFMA_64x128: return launch_t<SEMI, 2, 4, FMT>(p, s);
     case MFMA_64x32: return launch_t<SEMI, 2, 1, FMT>(p, s);
@@ -79,7 +77,6 @@ int leaf_mfma_tile_rows(int tile) {
   switch (tile) {
     case MFMA_64x64: return 64;
     case MFMA_64x128: return 64;
-    case MFMA_P_64x128: return 64;
     case MFMA_64x32: return 64;
     case MFMA_LDS_256x256: return 256;
     default: return 128;
@@ -90,7 +87,6 @@ int leaf_mfma_tile_cols(int tile) {
   switch (tile) {
     case MFMA_64x64: return 64;
     case MFMA_64x128: return 128;
-    case MFMA_P_64x128: return 128;
     case MFMA_64x32: return 32;
     case MFMA_LDS_256x256: return 256;
     default: return 64;

@@ -11,10 +11,8 @@ pytestmark = pytest.mark.gpu
 
 SEMIRINGS = [("gf2", oracle.GF2), ("bool", oracle.BOOLEAN)]
 LEAVES = [("valu", 1, 1), ("mfma128x64", 2, 1), ("mfma64x64", 2, 2), ("mfma64x128", 2, 3),
-          ("mfma64x32", 2, 4), ("mfma_lds256", 2, 5), ("mfma_p128x64", 2, 6),
-          ("mfma_p64x128", 2, 7), ("f4_128x64", 3, 1), ("f4_64x64", 3, 2),
-          ("f4_64x128", 3, 3), ("f4_64x32", 3, 4), ("f4_lds256", 3, 5), ("f4_p128x64", 3, 6),
-          ("f4_p64x128", 3, 7)]
+          ("mfma64x32", 2, 4), ("mfma_lds256", 2, 5), ("f4_128x64", 3, 1), ("f4_64x64", 3, 2),
+          ("f4_64x128", 3, 3), ("f4_64x32", 3, 4), ("f4_lds256", 3, 5)]
 
 
 @pytest.fixture(scope="module")
@@ -93,30 +91,6 @@ def test_transposed_b_and_accumulate(bmm, sname, sr, lname, leaf, tile):
     announce("accumulate", sname, lname)
     got = run(bmm, sr, leaf, tile, A, B, m, k, n, acc_init=C0)
     assert np.array_equal(got, (want ^ C0) if sr == oracle.GF2 else (want | C0))
-
-
-PERSIST_SHAPES = [(8192, 1024, 8192), (8000, 960, 8100), (4100, 1100, 4000), (2048, 64, 6000)]
-
-
-@pytest.mark.parametrize("leaf", [2, 3])
-@pytest.mark.parametrize("tile", [6, 7])
-def test_persistent_tiles_walk_many_tiles(bmm, leaf, tile):
-    """Shapes with more workgroup tiles than the persistent grid holds, so every
-    workgroup walks several: the next tile's first words are fetched during the
-    last step pair (k of 16 words), after the epilogue (odd step counts, tails),
-    and rows and columns that run past the ends (edge tiles)."""
-    for i, (m, k, n) in enumerate(PERSIST_SHAPES):
-        sr = oracle.GF2 if i % 2 == 0 else oracle.BOOLEAN
-        p = None if sr == oracle.GF2 else bmmgen.Dist.inv_sqrt(k)
-        A = gen(m, k, 40 + i, bmmgen.TAG_A, p)
-        B = gen(k, n, 40 + i, bmmgen.TAG_B, p)
-        C0 = gen(m, n, 40 + i, 0xC0)
-        want = oracle.mul(A, B, k, n, sr)
-        announce("persistent", leaf, tile, (m, k, n))
-        assert np.array_equal(run(bmm, sr, leaf, tile, A, B, m, k, n, b_t=True), want), (m, k, n)
-        announce("persistent accumulate", leaf, tile, (m, k, n))
-        got = run(bmm, sr, leaf, tile, A, B, m, k, n, acc_init=C0)
-        assert np.array_equal(got, (want ^ C0) if sr == oracle.GF2 else (want | C0)), (m, k, n)
 
 
 def test_k_zero_and_empty(bmm):

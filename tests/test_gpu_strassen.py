@@ -174,25 +174,6 @@ def test_strassen_product(bmm, m, k, n, depth, ds, leaf):
     assert np.array_equal(from_dev(Ad), A) and np.array_equal(from_dev(Bd), B)
 
 
-@pytest.mark.parametrize("tile", [6, 7])
-@pytest.mark.parametrize("depth,ds", [(3, 0), (4, 1)])
-def test_strassen_persistent_leaf(bmm, tile, depth, ds):
-    """Batched leaf launches with more tiles than the persistent grid (343 leaves of
-    512^3 at depth 3; 2401 of 256^3 at depth 4, an odd step count)."""
-    import torch
-    m = k = n = 4096
-    seed = 777 + depth + tile
-    A = bmmgen.fill_cpu(m, k, seed, bmmgen.TAG_A, bmmgen.Dist.half())
-    B = bmmgen.fill_cpu(k, n, seed, bmmgen.TAG_B, bmmgen.Dist.half())
-    opts = bmm.Options(leaf=2, tile=tile, depth_serial=ds, depth_parallel=depth - ds)
-    nbytes, _, _ = bmm.bmm_gf2_strassen_workspace(m, k, n, depth, opts)
-    ws = torch.empty(nbytes // 8 + 1, dtype=torch.int64, device="cuda")
-    Cd = empty_dev(m, words(n), fill=-1)
-    announce("strassen persistent leaf", tile, depth, ds)
-    bmm.bmm_gf2_strassen(to_dev(A), to_dev(B), Cd, m, k, n, ws, depth=depth, options=opts)
-    assert np.array_equal(from_dev(Cd), oracle.mul(A, B, k, n, oracle.GF2))
-
-
 SCHEME_CASES = [  # m, k, n, depth, depth_serial
     (512, 512, 512, 1, 0), (1024, 1024, 1024, 4, 1), (2048, 2048, 2048, 5, 2),
     (1024, 2048, 512, 2, 1), (768, 1536, 1024, 1, 1), (2048, 2048, 2048, 3, 0),
