@@ -108,3 +108,20 @@ def test_autotune_table_roundtrip(tmp_path):
     bmm.bmm_autotune_load(str(p))
     with pytest.raises(bmm.BmmError):
         bmm.bmm_autotune_set(bmm.GF2, 1, 1, 1, bmm.LEAF_MFMA_I8, 9)
+
+
+def test_leaf_choice_follows_the_table(tmp_path):
+    """bmm_leaf_choice is host-only: explicit options win, then the table, then the
+    default rule (128 x 64 tiles, 64 x 64 when the launch has fewer than 4096 waves)."""
+    import paper_1909_01554_amd as bmm
+    p = tmp_path / "t.txt"
+    p.write_text("leaf 1 4096 8192 4096 1 3 1 4 5\n")
+    bmm.bmm_autotune_load(str(p))
+    assert bmm.bmm_leaf_choice(bmm.BOOLEAN, 4096, 8192, 4096) == (3, 5)
+    assert bmm.bmm_leaf_choice(bmm.BOOLEAN, 4096, 8192, 4096, options=bmm.Options(leaf=2)) == (2, 4)
+    assert bmm.bmm_leaf_choice(bmm.BOOLEAN, 4096, 8192, 4096,
+                               options=bmm.Options(leaf=2, tile=3)) == (2, 3)
+    assert bmm.bmm_leaf_choice(bmm.GF2, 1 << 16, 1 << 16, 1 << 16) == (2, 1)
+    assert bmm.bmm_leaf_choice(bmm.GF2, 256, 256, 256) == (2, 2)
+    with pytest.raises(bmm.BmmError):
+        bmm.bmm_leaf_choice(7, 1, 1, 1)
