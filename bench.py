@@ -57,7 +57,8 @@ def parse():
     ap.add_argument("--no-schemes", action="store_true",
                     help="skip timing the GF(2) recursion with the chaining and "
                          "Strassen-Winograd schemes")
-    ap.add_argument("--mode", choices=["step", "leaf", "batched", "ooc", "tune"], default="step",
+    ap.add_argument("--mode", choices=["step", "leaf", "cubic", "batched", "ooc", "tune"],
+                    default="step",
                     help="leaf: one Boolean leaf launch plus a copy of known size (for "
                          "profiler counters); batched: 4096 uneven products in one "
                          "persistent launch; ooc: host-resident operands")
@@ -173,6 +174,62 @@ def run_batched(args, torch, np, bmm, bmmgen):
                                                         else PEAK_MFMA_I8_TOPS), 4)}), flush=True)
 
 
+def run_cubic(args, torch, np, bmm, bmmgen):
+    """The cubic products at one size (n = 65536 for the VALU-vs-int8 comparison):
+    GF(2) on Bernoulli(1/2) bits and Boolean on Bernoulli(n^-1/2) bits (P(c = 1) ~ 0.63),
+    B transposed once, then each leaf kind with its tuned or default tile; the median of
+    `steps` launches after `warmup` launches, each checked on 64 stratified rows."""
+    import oracle
+    n = args.n
+    seed = bmmgen.config_seed(1)
+    dev = torch.device("cuda:0")
+    bops = 2.0 * n ** 3
+    peaks = {bmm.LEAF_VALU: PEAK_VALU_FUSED_TBOPS, bmm.LEAF_MFMA_I8: PEAK_MFMA_I8_TOPS,
+             bmm.LEAF_MFMA_F4: PEAK_MFMA_F4_TOPS}
+    names = {bmm.LEAF_VALU: "valu", bmm.LEAF_MFMA_I8: "int8", bmm.LEAF_MFMA_F4: "fp4"}
+    out = {"mode": "cubic", "n": n}
+    rows = bmmgen.stratified_rows(n, 64, seed)
+    for sname, sr, dist in [("gf2", bmm.GF2, bmmgen.Dist.half()),
+                            ("boolean", bmm.BOOLEAN,
+                             bmmgen.Dist.pow2(max(1, (n.bit_length() - 1) // 2)))]:
+        A = torch.empty((n, n // 64), dtype=torch.int64, device=dev)
+        B = torch.empty_like(A)
+        BT = torch.empty_like(A)
+        C = torch.empty_like(A)
+        bmmgen.fill_tensor(A, n, n, seed, 0xA if sr == bmm.GF2 else 0x1A, dist)
+        bmmgen.fill_tensor(B, n, n, seed, 0xB if sr == bmm.GF2 else 0x1B, dist)
+        bmm.bmm_transpose(B, BT, n, n)
+        del B
+        Bh = bmmgen.fill_cpu(n, n, seed, 0xB if sr == bmm.GF2 else 0x1B, dist)
+        Ar = bmmgen.fill_rows_cpu(rows, n, seed, 0xA if sr == bmm.GF2 else 0x1A, dist)
+        want = oracle.rows(Ar, Bh, n, n, sr)
+        del Bh
+        fn = bmm.bmm_gf2 if sr == bmm.GF2 else bmm.bmm_boolean
+        for leaf in (bmm.LEAF_VALU, bmm.LEAF_MFMA_I8, bmm.LEAF_MFMA_F4):
+            o = bmm.Options(leaf=leaf)
+            _, tile = bmm.bmm_leaf_choice(sr, n, n, n, 1, o)
+            for _ in range(args.warmup):
+                fn(A, BT, C, n, n, n, options=o, b_transposed=True)
+            times = []
+            for _ in range(args.steps):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                fn(A, BT, C, n, n, n, options=o, b_transposed=True)
+                e1.record()
+                torch.cuda.synchronize()
+                times.append(e0.elapsed_time(e1) / 1e3)
+            t = sorted(times)[len(times) // 2]
+            got = C[rows].cpu().numpy().view(np.uint64)
+            out[f"{sname}_{names[leaf]}"] = {
+                "tile": tile, "seconds": round(t, 5), "pbops": round(bops / t / 1e15, 4),
+                "frac_of_peak": round(bops / t / 1e12 / peaks[leaf], 4),
+                "verified_rows": len(rows), "verified": bool(np.array_equal(got, want))}
+            log(f"[bench] cubic {sname} {names[leaf]}: {out[f'{sname}_{names[leaf]}']}")
+        del A, BT, C
+        torch.cuda.empty_cache()
+    print(json.dumps(out), flush=True)
+
+
 def run_ooc(args, torch, np, bmm, bmmgen):
     """Products with A, B, C in page-locked host memory, streamed through HBM in
     b x b blocks (copies on their own streams, overlapped with compute).  GF(2)
@@ -253,6 +310,8 @@ def main():
     if args.mode != "tune" and os.path.exists(tune_file):
         bmm.bmm_autotune_load(tune_file)
         log(f"[bench] loaded autotune table {tune_file}")
+    if args.mode == "cubic":
+        return run_cubic(args, torch, np, bmm, bmmgen)
     if args.mode == "batched":
         return run_batched(args, torch, np, bmm, bmmgen)
     if args.mode == "ooc":
