@@ -375,11 +375,12 @@ def main():
     if args.mode == "tune":
         out = {"mode": "tune", "n": n}
         # leaf table: the full-size cubic shapes, one timed launch per (leaf, tile) on the
-        # step's own buffers (the dense leaves take the same time on any bits), and the
+        # step's own inputs for that semiring (the matrix cores' rate depends on how many
+        # operand bits switch, so each semiring is timed on its own bit density), and the
         # Strassen leaf shapes of the admissible depths
-        for sr, name, A_, BT_, C_ in [(bmm.BOOLEAN, "boolean", Ab, BTb, Cb),
-                                      (bmm.GF2, "gf2", Ab, BTb, Cb)]:
-            bmm.bmm_transpose(Bb, BTb, n, n)
+        for sr, name, A_, B_ in [(bmm.BOOLEAN, "boolean", Ab, Bb), (bmm.GF2, "gf2", Ag, Bg)]:
+            bmm.bmm_transpose(B_, BTb, n, n)
+            BT_, C_ = BTb, Cb
             fn = bmm.bmm_boolean if sr == bmm.BOOLEAN else bmm.bmm_gf2
             best = {}
             for lf in (bmm.LEAF_VALU, bmm.LEAF_MFMA_I8, bmm.LEAF_MFMA_F4):

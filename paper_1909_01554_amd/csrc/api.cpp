@@ -729,13 +729,16 @@ int bmm_autotune_leaf(int semiring, int64_t m, int64_t k, int64_t n, int64_t bat
   hipEvent_t e0, e1;
   (void)hipEventCreate(&e0);
   (void)hipEventCreate(&e1);
-  (void)hipMemsetD32((hipDeviceptr_t)A, 0x5A5A5A5A, ba * nb / 4);
-  (void)hipMemsetD32((hipDeviceptr_t)BT, 0x3C3C3C3C, bb * nb / 4);
+  // dense random operands: the rate of the matrix cores depends on the bits they see
+  rc = check_hip(launch_random(A, (int64_t)(ba * nb / 8), 0x5EED0001ull, nullptr), "tuning data");
+  if (rc == BMM_OK)
+    rc = check_hip(launch_random(BT, (int64_t)(bb * nb / 8), 0x5EED0002ull, nullptr), "tuning data");
   std::vector<std::pair<int, int>> cands = {{BMM_LEAF_VALU, 1}};
   for (int t = 1; t <= MFMA_NUM_TILES; ++t) cands.push_back({BMM_LEAF_MFMA_I8, t});
   if (k < ((int64_t)1 << 24))
     for (int t = 1; t <= MFMA_NUM_TILES; ++t) cands.push_back({BMM_LEAF_MFMA_F4, t});
   for (auto [leaf, tile] : cands) {
+    if (rc != BMM_OK) break;
     LeafBatch p{A, kw, m * kw, BT, kw, n * kw, C, nw, m * nw, m, k, n, nb, 0};
     // a timed warm-up; launches longer than 0.2 s are timed once, shorter ones 3 more times
     (void)hipEventRecord(e0, nullptr);

@@ -62,7 +62,9 @@ __device__ __forceinline__ TileCoord xcd_tile(int64_t g, int64_t total, int64_t 
 
 // MFMA leaf variants (rows x cols of C per wave).
 enum MfmaTile { MFMA_128x64 = 0, MFMA_64x64 = 1, MFMA_64x128 = 2, MFMA_64x32 = 3,
-                MFMA_LDS_256x256 = 4, MFMA_NUM_TILES };
+                MFMA_LDS_256x256 = 4,
+                MFMA_DEEP_128x64 = 5,  // 128 x 64, 3-deep unrolled pipeline for k = 2048, 4096
+                MFMA_NUM_TILES };
 
 hipError_t launch_leaf_mfma(int semiring, const LeafBatch& p, int tile, hipStream_t s);
 // The same tiles on E2M1 (fp4) operands with exact fp32 sums; requires k < 2^24.
@@ -116,6 +118,8 @@ hipError_t launch_copy(const uint64_t* src, int64_t lds, uint64_t* dst, int64_t 
 // dst ^= src for rows x words matrices.
 hipError_t launch_xor(const uint64_t* src, int64_t lds, uint64_t* dst, int64_t ldd, int64_t rows,
                       int64_t words, hipStream_t s);
+// Fill `words` contiguous words with dense pseudo-random bits (autotuner buffers).
+hipError_t launch_random(uint64_t* dst, int64_t words, uint64_t seed, hipStream_t s);
 // Zero a rows x words matrix (a fill kernel, safe under graph capture).
 hipError_t launch_zero(uint64_t* dst, int64_t ld, int64_t rows, int64_t words, hipStream_t s);
 

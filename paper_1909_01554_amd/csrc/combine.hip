@@ -202,6 +202,23 @@ __global__ __launch_bounds__(256) void xor_kernel(const uint64_t* __restrict__ s
   }
 }
 
+// Pseudo-random words for the autotuner's timing buffers (the matrix cores' rate
+// depends on how many operand bits switch, so tuning runs on dense random bits):
+// the 64-bit finalizer of MurmurHash3 applied to seed + index.
+__global__ __launch_bounds__(256) void random_kernel(uint64_t* __restrict__ dst, int64_t words,
+                                                     uint64_t seed) {
+  const int64_t gstride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < words; e += gstride) {
+    uint64_t z = seed + (uint64_t)e;
+    z ^= z >> 33;
+    z *= 0xFF51AFD7ED558CCDull;
+    z ^= z >> 33;
+    z *= 0xC4CEB9FE1A85EC53ull;
+    z ^= z >> 33;
+    dst[e] = z;
+  }
+}
+
 __global__ __launch_bounds__(256) void zero_kernel(uint64_t* __restrict__ dst, int64_t ld,
                                                    int64_t rows, int64_t words) {
   const int64_t total = rows * words;
@@ -345,6 +362,12 @@ hipError_t launch_xor(const uint64_t* src, int64_t lds, uint64_t* dst, int64_t l
   if (total <= 0) return hipSuccess;
   hipLaunchKernelGGL(xor_kernel, dim3(grid_for(total)), dim3(256), 0, s, src, lds, dst, ldd, rows,
                      words);
+  return hipGetLastError();
+}
+
+hipError_t launch_random(uint64_t* dst, int64_t words, uint64_t seed, hipStream_t s) {
+  if (words <= 0) return hipSuccess;
+  hipLaunchKernelGGL(random_kernel, dim3(grid_for(words)), dim3(256), 0, s, dst, words, seed);
   return hipGetLastError();
 }
 

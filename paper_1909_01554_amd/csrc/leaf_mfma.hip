@@ -11,10 +11,11 @@
 // bits straight from its row of A (or of B transposed) and expands them in
 // registers.  The order of k inside a dot product is free as long as A and B
 // use the same one, so a 32-bit half x of a word yields the eight dwords
-// x >> d (d = 0..7): byte e of dword d carries bit 8e + d of x in its lowest
-// bit.  For GF(2) only that lowest bit matters (a product of two bytes is odd
-// iff both low bits are 1), so one shift makes four operand bytes; the Boolean
-// count needs exact 0/1 bytes and adds a mask with 0x01010101.
+// (x >> d) & 0x01010101 (d = 0..7): byte e of dword d is bit 8e + d of x, 0 or
+// 1.  GF(2) parity alone would only need the low bit of each byte, but
+// operand bytes holding the other random bits too make the matrix cores
+// switch far more on dense inputs and run at a lower rate, so both semirings
+// feed exact 0/1 bytes.
 //
 // The result bits go back to packed rows with wave ballots: accumulator
 // register v of a 32x32 block holds row 8*(v/4) + (v%4) in lanes 0..31 and
@@ -26,7 +27,7 @@ namespace bmm {
 namespace {
 
 // Each workgroup owns 2 x 2 wave tiles; workgroups are ordered for L2 reuse per XCD.
-template <int SEMI, int RA, int RB, int KV, int FMT>
+template <int SEMI, int RA, int RB, int KV, int FMT, int NB = 2, int STEPS = 0>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void leaf_mfma_kernel(
     LeafBatch p, int64_t tiles_m, int64_t tiles_n) {
   const int64_t grid_m = (tiles_m + 1) >> 1, grid_n = (tiles_n + 1) >> 1;
@@ -36,12 +37,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void l
   const int64_t tn = 2 * c.tn + (w & 1);
   if (c.b >= p.batch || tm >= tiles_m || tn >= tiles_n) return;  // uniform per wave
   const int64_t b = c.b;
-  mfma::tile<SEMI, RA, RB, KV, FMT>(p.A + b * p.strideA, p.lda, p.BT + b * p.strideB, p.ldbt,
+  mfma::tile<SEMI, RA, RB, KV, FMT, NB, STEPS>(p.A + b * p.strideA, p.lda, p.BT + b * p.strideB, p.ldbt,
                                     p.C + b * p.strideC, p.ldc, p.m, p.k, p.n, tm, tn,
                                     p.accumulate);
 }
 
-template <int SEMI, int RA, int RB, int FMT>
+// DEEP: int8 leaves of the recursion's lengths (k = 2048 or 4096 bits, 16-byte
+// aligned) run a fully unrolled 3-deep load pipeline; all else takes the 2-deep loop.
+template <int SEMI, int RA, int RB, int FMT, bool DEEP = false>
 hipError_t launch_t(const LeafBatch& p, hipStream_t s) {
   constexpr int TM = 32 * RA, TN = 32 * RB;
   const int64_t tiles_m = (p.m + TM - 1) / TM;
@@ -51,7 +54,14 @@ hipError_t launch_t(const LeafBatch& p, hipStream_t s) {
   if (blocks == 0) return hipSuccess;
   const bool aligned16 = ((reinterpret_cast<uintptr_t>(p.A) | reinterpret_cast<uintptr_t>(p.BT)) & 15) == 0 &&
                          ((p.lda | p.ldbt | p.strideA | p.strideB) & 1) == 0;
-  if (aligned16)
+  // the unrolled pipeline is built for the int8 format only
+  if (DEEP && FMT == mfma::FMT_I8 && aligned16 && p.k == 2048)
+    hipLaunchKernelGGL((leaf_mfma_kernel<SEMI, RA, RB, 2, FMT, 3, 8>), dim3((unsigned)blocks),
+                       dim3(256), 0, s, p, tiles_m, tiles_n);
+  else if (DEEP && FMT == mfma::FMT_I8 && aligned16 && p.k == 4096)
+    hipLaunchKernelGGL((leaf_mfma_kernel<SEMI, RA, RB, 2, FMT, 3, 16>), dim3((unsigned)blocks),
+                       dim3(256), 0, s, p, tiles_m, tiles_n);
+  else if (aligned16)
     hipLaunchKernelGGL((leaf_mfma_kernel<SEMI, RA, RB, 2, FMT>), dim3((unsigned)blocks), dim3(256), 0, s,
                        p, tiles_m, tiles_n);
   else
@@ -64,6 +74,7 @@ template <int SEMI, int FMT>
 hipError_t launch_semi(const LeafBatch& p, int tile, hipStream_t s) {
   switch (tile) {
     case MFMA_LDS_256x256: return launch_leaf_mfma_lds(SEMI, FMT, p, s);
+    case MFMA_DEEP_128x64: return launch_t<SEMI, 4, 2, FMT, true>(p, s);
     case MFMA_64x64: return launch_t<SEMI, 2, 2, FMT>(p, s);
     case MFMA_64x128: return launch_t<SEMI, 2, 4, FMT>(p, s);
     case MFMA_64x32: return launch_t<SEMI, 2, 1, FMT>(p, s);

@@ -39,15 +39,15 @@ __device__ __forceinline__ v8i expand_f4(uint32_t x) {
   return o;
 }
 
+// Four int8 operand dwords from bits first .. first+3 of every byte of x: each
+// byte becomes exactly 0 or 1.  (For GF(2) the parity of the count would only
+// need the low bit of each byte, but bytes that keep the other random bits make
+// the matrix cores switch far more and run slower on dense inputs.)
 template <int SEMI>
 __device__ __forceinline__ v4i expand4(uint32_t x, int first) {
   v4i o;
 #pragma unroll
-  for (int d = 0; d < 4; ++d) {
-    uint32_t e = x >> (first + d);
-    if (SEMI == BOOLEAN) e &= 0x01010101u;
-    o[d] = (int)e;
-  }
+  for (int d = 0; d < 4; ++d) o[d] = (int)((x >> (first + d)) & 0x01010101u);
   return o;
 }
 
@@ -141,7 +141,11 @@ __device__ __forceinline__ void epilogue(const typename Acc<FMT>::type (&acc)[RA
 
 // KV = 64-bit words per lane per load (1: 8-byte loads, 2: 16-byte loads when
 // the operands are 16-byte aligned).  Lane half h takes words 2*KV*step + KV*h + v.
-template <int SEMI, int RA, int RB, int KV, int FMT>
+// STEPS > 0: the launch guarantees exactly STEPS full steps and no tail words
+// (k = 128 * KV * STEPS bits); the loop then unrolls completely, so the
+// compiler knows every load in flight, and NB register buffers keep the words
+// of step st + NB - 1 in flight while step st computes.
+template <int SEMI, int RA, int RB, int KV, int FMT, int NB = 2, int STEPS = 0>
 __device__ __forceinline__ void tile(const uint64_t* __restrict__ A, int64_t lda,
                                      const uint64_t* __restrict__ BT, int64_t ldbt,
                                      uint64_t* __restrict__ Cm, int64_t ldc, int64_t m,
@@ -208,6 +212,20 @@ __device__ __forceinline__ void tile(const uint64_t* __restrict__ A, int64_t lda
 #pragma unroll
     for (int v = 0; v < KV; ++v) mfma_word<SEMI, RA, RB, FMT>(xa[v], xb[v], acc);
   };
+  if constexpr (STEPS > 0) {
+    static_assert(STEPS >= NB, "an unrolled pipeline needs at least NB steps");
+    uint64_t xa[NB][KV][RA], xb[NB][KV][RB];
+#pragma unroll
+    for (int i = 0; i + 1 < NB; ++i) fetch(i, xa[i], xb[i]);
+#pragma unroll
+    for (int s = 0; s < STEPS; ++s) {
+      if (s + NB - 1 < STEPS) fetch(s + NB - 1, xa[(s + NB - 1) % NB], xb[(s + NB - 1) % NB]);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(xa[s % NB], xb[s % NB]);
+    }
+    epilogue<SEMI, RA, RB, FMT>(acc, Cm, ldc, m, n, tm, tn, accumulate);
+    return;
+  }
   if (full_steps > 0) fetch(0, a0, b0);
   int64_t st = 0;
   // sched_barrier(0) keeps the scheduler from sinking the loads below the MFMAs

@@ -174,6 +174,25 @@ def test_strassen_product(bmm, m, k, n, depth, ds, leaf):
     assert np.array_equal(from_dev(Ad), A) and np.array_equal(from_dev(Bd), B)
 
 
+@pytest.mark.parametrize("leaf", [2, 3])
+@pytest.mark.parametrize("m,k,n,depth", [(8192, 8192, 8192, 2), (8192, 8192, 4096, 1),
+                                         (8192, 4096, 2048, 1)])
+def test_strassen_deep_pipeline_leaf(bmm, leaf, m, k, n, depth):
+    """Tile 6: leaves with k = 2048 or 4096 bits run the fully unrolled 3-deep pipeline."""
+    import torch
+    seed = 901 + m + depth + leaf
+    A = bmmgen.fill_cpu(m, k, seed, bmmgen.TAG_A, bmmgen.Dist.half())
+    B = bmmgen.fill_cpu(k, n, seed, bmmgen.TAG_B, bmmgen.Dist.half())
+    opts = bmm.Options(leaf=leaf, tile=6, depth_serial=0, depth_parallel=depth)
+    nbytes, _, _ = bmm.bmm_gf2_strassen_workspace(m, k, n, depth, opts)
+    ws = torch.empty(nbytes // 8 + 1, dtype=torch.int64, device="cuda")
+    Cd = empty_dev(m, words(n), fill=-1)
+    announce("strassen deep leaf", leaf, m, k, n, depth)
+    bmm.bmm_gf2_strassen(to_dev(A), to_dev(B), Cd, m, k, n, ws, depth=depth, options=opts)
+    rows = bmmgen.stratified_rows(m, 128, seed)
+    assert np.array_equal(from_dev(Cd)[rows], oracle.rows(A[rows], B, k, n, oracle.GF2))
+
+
 SCHEME_CASES = [  # m, k, n, depth, depth_serial
     (512, 512, 512, 1, 0), (1024, 1024, 1024, 4, 1), (2048, 2048, 2048, 5, 2),
     (1024, 2048, 512, 2, 1), (768, 1536, 1024, 1, 1), (2048, 2048, 2048, 3, 0),
