@@ -28,7 +28,7 @@ PEAK_VALU_FUSED_TBOPS = 5033.2
 # FETCH_SIZE and WRITE_SIZE of the int8 leaf with 64 x 128 tiles (the tuned tile), scaled
 # by the same counters on a 4 GiB copy in the same runs (reads x 2.0, writes x 1.0); see
 # profiles/pmc_traffic_leaf_boolean_n262144.md.  Valid for that kernel only.
-MEASURED_TRAFFIC = {("mfma", 3, 1 << 18): (8323545282.1 * 2.0 + 20985597.5) * 1024}
+MEASURED_TRAFFIC = {("mfma", 3, 1 << 18): (8428913479.5 * 2.0 + 21601547.0) * 1024}
 
 
 def log(*a):

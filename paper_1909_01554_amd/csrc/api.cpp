@@ -117,8 +117,8 @@ struct TuneVal {
 std::map<TuneKey, TuneVal> g_tune;
 // Strassen (depth, serial depth) per shape, from bmm_autotune_strassen.
 std::map<std::tuple<int64_t, int64_t, int64_t>, std::pair<int, int>> g_depth;
-// Batched plans: (problem count, floor(log2(total ops))) -> (leaf, tile).
-std::map<std::pair<int64_t, int>, std::pair<int, int>> g_batched;
+// Batched plans: (problem count, floor(log2(total ops))) -> (leaf, tile, workgroups per CU).
+std::map<std::pair<int64_t, int>, std::tuple<int, int, int>> g_batched;
 
 int ops_bucket(double ops) {
   int b = 0;
@@ -537,18 +537,17 @@ int bmm_gf2_strassen(const uint64_t* A, int64_t lda, const uint64_t* B, int64_t 
 
 namespace bmm {
 
-bool batched_tuned(int64_t count, double ops, int* leaf, int* tile) {
+bool batched_tuned(int64_t count, double ops, int* leaf, int* tile, int* wg_per_cu) {
   std::lock_guard<std::mutex> lock(g_mu);
   auto it = g_batched.find({count, ops_bucket(ops)});
   if (it == g_batched.end()) return false;
-  *leaf = it->second.first;
-  *tile = it->second.second;
+  std::tie(*leaf, *tile, *wg_per_cu) = it->second;
   return true;
 }
 
-void batched_tune_set(int64_t count, double ops, int leaf, int tile) {
+void batched_tune_set(int64_t count, double ops, int leaf, int tile, int wg_per_cu) {
   std::lock_guard<std::mutex> lock(g_mu);
-  g_batched[{count, ops_bucket(ops)}] = {leaf, tile};
+  g_batched[{count, ops_bucket(ops)}] = {leaf, tile, wg_per_cu};
 }
 
 hipError_t to_alt_basis(uint64_t* C, int64_t ldc, int64_t rows, int64_t words, int depth,
@@ -871,7 +870,7 @@ int bmm_autotune_save(const char* path) {
   f << "# bmm autotune table\n"
        "# leaf semiring m k n batch_bucket best_leaf tile_valu tile_mfma_i8 tile_mfma_f4\n"
        "# depth m k n depth depth_serial\n"
-       "# batched count log2_ops leaf tile\n";
+       "# batched count log2_ops leaf tile workgroups_per_cu\n";
   for (auto& [key, val] : g_tune)
     f << "leaf " << key.semiring << ' ' << key.m << ' ' << key.k << ' ' << key.n << ' '
       << key.batch << ' ' << val.best_leaf << ' ' << val.tile[1] << ' ' << val.tile[2] << ' '
@@ -880,8 +879,8 @@ int bmm_autotune_save(const char* path) {
     f << "depth " << std::get<0>(key) << ' ' << std::get<1>(key) << ' ' << std::get<2>(key)
       << ' ' << val.first << ' ' << val.second << '\n';
   for (auto& [key, val] : g_batched)
-    f << "batched " << key.first << ' ' << key.second << ' ' << val.first << ' ' << val.second
-      << '\n';
+    f << "batched " << key.first << ' ' << key.second << ' ' << std::get<0>(val) << ' '
+      << std::get<1>(val) << ' ' << std::get<2>(val) << '\n';
   return f ? BMM_OK : fail(BMM_E_INVAL, "write failed: %s", path);
 }
 
@@ -911,12 +910,13 @@ int bmm_autotune_load(const char* path) {
       if (d < 0 || ds < 0 || ds > d) return fail(BMM_E_INVAL, "bad depth line: %s", line.c_str());
       std::lock_guard<std::mutex> lock(g_mu);
       g_depth[{m, k, n}] = {d, ds};
-    } else if (sscanf(line.c_str(), "batched %lld %d %d %d", &m, &d, &leaf, &t1) == 4) {
+    } else if (sscanf(line.c_str(), "batched %lld %d %d %d %d", &m, &d, &leaf, &t1, &t2) >= 4) {
+      if (sscanf(line.c_str(), "batched %lld %d %d %d %d", &m, &d, &leaf, &t1, &t2) == 4) t2 = 4;
       if (m <= 0 || d < 0 || (leaf != BMM_LEAF_MFMA_I8 && leaf != BMM_LEAF_MFMA_F4) ||
-          (t1 != 1 && t1 != 2))
+          (t1 != 1 && t1 != 2) || t2 < 1 || t2 > 64)
         return fail(BMM_E_INVAL, "bad batched line: %s", line.c_str());
       std::lock_guard<std::mutex> lock(g_mu);
-      g_batched[{m, d}] = {leaf, t1};
+      g_batched[{m, d}] = {leaf, t1, t2};
     } else {
       return fail(BMM_E_INVAL, "bad line in %s: %s", path, line.c_str());
     }

@@ -47,7 +47,9 @@ int validate_problem(const bmm_problem& p, int64_t i) {
   return BMM_OK;
 }
 
-int build_plan(const bmm_problem* problems, int64_t count, const bmm_options* opt, Plan* out) {
+// wg_per_cu > 0 fixes the persistent grid (workgroups per CU); 0 takes the record.
+int build_plan(const bmm_problem* problems, int64_t count, const bmm_options* opt,
+               int wg_per_cu, Plan* out) {
   if (count < 0 || (count > 0 && !problems)) return bfail(BMM_E_INVAL, "bad problem list");
   std::vector<int64_t> order;
   double ops = 0;
@@ -65,11 +67,13 @@ int build_plan(const bmm_problem* problems, int64_t count, const bmm_options* op
   // count and total work, else int8 with 64 x 64 tiles
   int leaf = opt ? opt->leaf : BMM_LEAF_AUTO;
   int tile = opt ? opt->tile : 0;
-  int tl = 0, tt = 0;
-  if ((leaf == BMM_LEAF_AUTO || tile <= 0) && batched_tuned(count, ops, &tl, &tt)) {
+  int tl = 0, tt = 0, tw = 0;
+  if (batched_tuned(count, ops, &tl, &tt, &tw)) {
     if (leaf == BMM_LEAF_AUTO) leaf = tl;
     if (tile <= 0) tile = tt;
+    if (wg_per_cu <= 0) wg_per_cu = tw;
   }
+  if (wg_per_cu <= 0) wg_per_cu = 4;
   if (leaf == BMM_LEAF_AUTO) leaf = BMM_LEAF_MFMA_I8;
   if (tile <= 0) tile = 2;
   if (leaf != BMM_LEAF_MFMA_I8 && leaf != BMM_LEAF_MFMA_F4)
@@ -113,7 +117,7 @@ int build_plan(const bmm_problem* problems, int64_t count, const bmm_options* op
   if (hipGetDevice(&P.device) != hipSuccess) return bfail(BMM_E_DEVICE, "hipGetDevice");
   int cus = 256;
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, P.device);
-  P.grid = std::max(1, cus * 4);
+  P.grid = std::max(1, cus * wg_per_cu);
   if (P.count > 0) {
     if (hipMalloc((void**)&P.descs, sizeof(BatchedDesc) * host.size()) != hipSuccess ||
         hipMalloc((void**)&P.begins, sizeof(uint32_t) * begins.size()) != hipSuccess ||
@@ -145,7 +149,7 @@ int bmm_batched_plan_create(const bmm_problem* problems, int64_t count,
                             const bmm_options* opt, void** plan_out) {
   if (!plan_out) return bfail(BMM_E_INVAL, "null plan_out");
   Plan* P = new Plan();
-  int rc = build_plan(problems, count, opt, P);
+  int rc = build_plan(problems, count, opt, 0, P);
   if (rc != BMM_OK) {
     delete P;
     return rc;
@@ -189,44 +193,52 @@ int bmm_autotune_batched(const bmm_problem* problems, int64_t count, int* leaf_o
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     return bfail(BMM_E_DEVICE, "event create");
   double best = 1e30;
-  int best_leaf = BMM_LEAF_MFMA_I8, best_tile = 2, rc = BMM_OK;
+  int best_leaf = BMM_LEAF_MFMA_I8, best_tile = 2, best_wpc = 4, rc = BMM_OK;
   for (int leaf : {BMM_LEAF_MFMA_I8, BMM_LEAF_MFMA_F4}) {
     for (int tile : {1, 2}) {
-      bmm_options o;
-      bmm_options_init(&o);
-      o.leaf = leaf;
-      o.tile = tile;
-      void* plan = nullptr;
-      rc = bmm_batched_plan_create(problems, count, &o, &plan);
-      if (rc == BMM_E_UNSUPPORTED) {  // e.g. fp4 with k >= 2^24: not a candidate
-        rc = BMM_OK;
-        continue;
+      for (int wpc : {2, 4, 8}) {
+        bmm_options o;
+        bmm_options_init(&o);
+        o.leaf = leaf;
+        o.tile = tile;
+        Plan* plan = new Plan();
+        rc = build_plan(problems, count, &o, wpc, plan);
+        if (rc == BMM_E_UNSUPPORTED) {  // e.g. fp4 with k >= 2^24: not a candidate
+          delete plan;
+          rc = BMM_OK;
+          continue;
+        }
+        if (rc != BMM_OK) {
+          delete plan;
+          break;
+        }
+        rc = bmm_batched_plan_launch(plan, nullptr);  // warm-up
+        if (rc == BMM_OK) {
+          (void)hipEventRecord(e0, nullptr);
+          rc = bmm_batched_plan_launch(plan, nullptr);
+          (void)hipEventRecord(e1, nullptr);
+        }
+        float ms = 0.f;
+        if (rc == BMM_OK && (hipEventSynchronize(e1) != hipSuccess ||
+                             hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+          rc = bfail(BMM_E_DEVICE, "autotune timing: %s", hipGetErrorString(hipGetLastError()));
+        bmm_batched_plan_destroy(plan);
+        if (rc != BMM_OK) break;
+        if (ms * 1e-3 < best) {
+          best = ms * 1e-3;
+          best_leaf = leaf;
+          best_tile = tile;
+          best_wpc = wpc;
+        }
       }
       if (rc != BMM_OK) break;
-      rc = bmm_batched_plan_launch(plan, nullptr);  // warm-up
-      if (rc == BMM_OK) {
-        (void)hipEventRecord(e0, nullptr);
-        rc = bmm_batched_plan_launch(plan, nullptr);
-        (void)hipEventRecord(e1, nullptr);
-      }
-      float ms = 0.f;
-      if (rc == BMM_OK && (hipEventSynchronize(e1) != hipSuccess ||
-                           hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
-        rc = bfail(BMM_E_DEVICE, "autotune timing: %s", hipGetErrorString(hipGetLastError()));
-      bmm_batched_plan_destroy(plan);
-      if (rc != BMM_OK) break;
-      if (ms * 1e-3 < best) {
-        best = ms * 1e-3;
-        best_leaf = leaf;
-        best_tile = tile;
-      }
     }
     if (rc != BMM_OK) break;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc != BMM_OK) return rc;
-  batched_tune_set(count, ops, best_leaf, best_tile);
+  batched_tune_set(count, ops, best_leaf, best_tile, best_wpc);
   if (leaf_out) *leaf_out = best_leaf;
   if (tile_out) *tile_out = best_tile;
   if (seconds_out) *seconds_out = best;

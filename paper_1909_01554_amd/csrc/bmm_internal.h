@@ -143,11 +143,11 @@ hipError_t launch_batched_persistent(const BatchedDesc* descs, const uint32_t* b
 int batched_tile_rows(int tile);
 int batched_tile_cols(int tile);
 
-// Batched-plan choices recorded by the autotuner, keyed by the problem count
-// and the total work rounded to a power of two (kept with the other autotune
-// tables).
-bool batched_tuned(int64_t count, double ops, int* leaf, int* tile);
-void batched_tune_set(int64_t count, double ops, int leaf, int tile);
+// Batched-plan choices recorded by the autotuner (leaf kind, tile, persistent
+// workgroups per CU), keyed by the problem count and the total work rounded to a
+// power of two (kept with the other autotune tables).
+bool batched_tuned(int64_t count, double ops, int* leaf, int* tile, int* wg_per_cu);
+void batched_tune_set(int64_t count, double ops, int leaf, int tile, int wg_per_cu);
 
 }  // namespace bmm
 
