@@ -103,7 +103,9 @@ void bmm_options_init(bmm_options* opt);
  * C: m x n (pitch ldc).  m, k, n >= 0; zero sizes are valid and do nothing
  * (k = 0 writes C = 0 unless accumulating).  Unless B is passed transposed the
  * library transposes it into a cached device scratch buffer (which may call
- * hipMalloc on first use or growth; pass B^T to avoid that).
+ * hipMalloc on first use or growth, and synchronizes the device when it grows).
+ * That buffer is shared by all such calls on a device, so calls on different
+ * streams that may overlap must pass B^T (BMM_FLAG_B_TRANSPOSED).
  * Errors: BMM_E_INVAL (negative size, null pointer with nonzero size, pitch too
  * small, C overlapping A or B), BMM_E_NOMEM, BMM_E_DEVICE. */
 int bmm_gf2(const uint64_t* A, int64_t lda, const uint64_t* B, int64_t ldb, uint64_t* C,

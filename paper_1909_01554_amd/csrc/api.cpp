@@ -162,6 +162,8 @@ int run_leaf(int semiring, int leaf, int tile, const LeafBatch& p, hipStream_t s
   if (leaf == BMM_LEAF_VALU) {
     e = launch_leaf_valu(semiring, p, tile - 1, s);
   } else if (leaf == BMM_LEAF_MFMA_I8) {
+    if (p.k >= ((int64_t)1 << 31))
+      return fail(BMM_E_UNSUPPORTED, "the int8 leaf counts exactly only for k < 2^31");
     e = launch_leaf_mfma(semiring, p, tile - 1, s);
   } else if (leaf == BMM_LEAF_MFMA_F4) {
     if (p.k >= ((int64_t)1 << 24))

@@ -81,6 +81,8 @@ int build_plan(const bmm_problem* problems, int64_t count, const bmm_options* op
   if (tile != 1 && tile != 2) return bfail(BMM_E_INVAL, "batched tile must be 1 or 2");
   if (leaf == BMM_LEAF_MFMA_F4 && kmax >= ((int64_t)1 << 24))
     return bfail(BMM_E_UNSUPPORTED, "the fp4 leaf counts exactly only for k < 2^24");
+  if (kmax >= ((int64_t)1 << 31))
+    return bfail(BMM_E_UNSUPPORTED, "the int8 leaf counts exactly only for k < 2^31");
   std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
     return problems[a].k > problems[b].k;
   });
