@@ -46,7 +46,8 @@ def parse():
     ap.add_argument("--tune-file", default=None,
                     help="autotune table to load (default: the package's table for gfx950)")
     ap.add_argument("--depth-serial", type=int, default=-1)
-    ap.add_argument("--tile", type=int, default=0, help="MFMA leaf tile variant (0 = auto)")
+    ap.add_argument("--tile", type=int, default=0,
+                    help="tile variant of the timed leaf kind (0 = the autotune table's)")
     ap.add_argument("--no-valu", action="store_true", help="skip the VALU-leaf side step")
     ap.add_argument("--cpu-rows", type=int, default=256,
                     help="rows of the GF(2) product the oracle computes for the CPU baseline")
@@ -342,7 +343,8 @@ def main():
         return [torch.cuda.Event(enable_timing=True) for _ in range(4)]
 
     def opts(leaf):
-        return bmm.Options(leaf=leaf, tile=args.tile if leaf != bmm.LEAF_VALU else 0,
+        # --tile applies to the timed leaf kind only; side steps take their tuned tiles
+        return bmm.Options(leaf=leaf, tile=args.tile if leaf == LEAF[args.leaf] else 0,
                            depth_serial=args.depth_serial,
                            depth_parallel=-1 if args.depth_serial < 0 else
                            args.depth - args.depth_serial)
