@@ -43,8 +43,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void l
 }
 
 // DEEP: int8 leaves of the recursion's lengths (k = 2048 or 4096 bits, 16-byte
-// aligned) run a fully unrolled 3-deep load pipeline; all else takes the 2-deep loop.
-template <int SEMI, int RA, int RB, int FMT, bool DEEP = false>
+// aligned) run a fully unrolled 3-deep load pipeline.  CHUNKED: aligned int8 leaves
+// run the 2-deep pipeline as a loop over fully unrolled chunks of 12 steps, which
+// leaves the compiler's conservative wait for outstanding loads at the loop's
+// back edge once per chunk instead of once per step pair.  All else takes the
+// 2-deep loop.
+template <int SEMI, int RA, int RB, int FMT, bool DEEP = false, bool CHUNKED = false>
 hipError_t launch_t(const LeafBatch& p, hipStream_t s) {
   constexpr int TM = 32 * RA, TN = 32 * RB;
   const int64_t tiles_m = (p.m + TM - 1) / TM;
@@ -54,14 +58,28 @@ hipError_t launch_t(const LeafBatch& p, hipStream_t s) {
   if (blocks == 0) return hipSuccess;
   const bool aligned16 = ((reinterpret_cast<uintptr_t>(p.A) | reinterpret_cast<uintptr_t>(p.BT)) & 15) == 0 &&
                          ((p.lda | p.ldbt | p.strideA | p.strideB) & 1) == 0;
-  // the unrolled pipeline is built for the int8 format only
-  if (DEEP && FMT == mfma::FMT_I8 && aligned16 && p.k == 2048)
-    hipLaunchKernelGGL((leaf_mfma_kernel<SEMI, RA, RB, 2, FMT, 3, 8>), dim3((unsigned)blocks),
-                       dim3(256), 0, s, p, tiles_m, tiles_n);
-  else if (DEEP && FMT == mfma::FMT_I8 && aligned16 && p.k == 4096)
-    hipLaunchKernelGGL((leaf_mfma_kernel<SEMI, RA, RB, 2, FMT, 3, 16>), dim3((unsigned)blocks),
-                       dim3(256), 0, s, p, tiles_m, tiles_n);
-  else if (aligned16)
+  const dim3 g((unsigned)blocks), b(256);
+  // the unrolled pipelines are built for the int8 format only (fp4 operands spill)
+  if constexpr (DEEP && FMT == mfma::FMT_I8) {
+    if (aligned16 && p.k == 2048) {
+      hipLaunchKernelGGL((leaf_mfma_kernel<SEMI, RA, RB, 2, FMT, 3, 8>), g, b, 0, s, p, tiles_m,
+                         tiles_n);
+      return hipGetLastError();
+    }
+    if (aligned16 && p.k == 4096) {
+      hipLaunchKernelGGL((leaf_mfma_kernel<SEMI, RA, RB, 2, FMT, 3, 16>), g, b, 0, s, p, tiles_m,
+                         tiles_n);
+      return hipGetLastError();
+    }
+  }
+  if constexpr (CHUNKED && FMT == mfma::FMT_I8) {
+    if (aligned16) {
+      hipLaunchKernelGGL((leaf_mfma_kernel<SEMI, RA, RB, 2, FMT, 2, -12>), g, b, 0, s, p,
+                         tiles_m, tiles_n);
+      return hipGetLastError();
+    }
+  }
+  if (aligned16)
     hipLaunchKernelGGL((leaf_mfma_kernel<SEMI, RA, RB, 2, FMT>), dim3((unsigned)blocks), dim3(256), 0, s,
                        p, tiles_m, tiles_n);
   else
@@ -75,6 +93,7 @@ hipError_t launch_semi(const LeafBatch& p, int tile, hipStream_t s) {
   switch (tile) {
     case MFMA_LDS_256x256: return launch_leaf_mfma_lds(SEMI, FMT, p, s);
     case MFMA_DEEP_128x64: return launch_t<SEMI, 4, 2, FMT, true>(p, s);
+    case MFMA_CHUNK_64x128: return launch_t<SEMI, 2, 4, FMT, false, true>(p, s);
     case MFMA_64x64: return launch_t<SEMI, 2, 2, FMT>(p, s);
     case MFMA_64x128: return launch_t<SEMI, 2, 4, FMT>(p, s);
     case MFMA_64x32: return launch_t<SEMI, 2, 1, FMT>(p, s);
@@ -88,6 +107,7 @@ int leaf_mfma_tile_rows(int tile) {
   switch (tile) {
     case MFMA_64x64: return 64;
     case MFMA_64x128: return 64;
+    case MFMA_CHUNK_64x128: return 64;
     case MFMA_64x32: return 64;
     case MFMA_LDS_256x256: return 256;
     default: return 128;
@@ -98,6 +118,7 @@ int leaf_mfma_tile_cols(int tile) {
   switch (tile) {
     case MFMA_64x64: return 64;
     case MFMA_64x128: return 128;
+    case MFMA_CHUNK_64x128: return 128;
     case MFMA_64x32: return 32;
     case MFMA_LDS_256x256: return 256;
     default: return 64;

@@ -226,7 +226,40 @@ __device__ __forceinline__ void tile(const uint64_t* __restrict__ A, int64_t lda
     epilogue<SEMI, RA, RB, FMT>(acc, Cm, ldc, m, n, tm, tn, accumulate);
     return;
   }
+  if constexpr (STEPS < 0) {
+    // Long k: a loop over chunks of CH = -STEPS steps, each fully unrolled, with NB
+    // buffers rotating across chunk boundaries (CH is a multiple of NB, so every chunk
+    // starts on buffer 0); the tail after the last whole chunk drains with guarded loads.
+    constexpr int CH = -STEPS;
+    static_assert(CH % NB == 0, "a chunk must hold whole rotations");
+    uint64_t xa[NB][KV][RA], xb[NB][KV][RB];
+    if (full_steps >= CH + NB) {
+#pragma unroll
+      for (int i = 0; i + 1 < NB; ++i) fetch(i, xa[i], xb[i]);
+      int64_t st = 0;
+      for (; st + CH + NB - 1 <= full_steps; st += CH) {
+#pragma unroll
+        for (int s = 0; s < CH; ++s) {
+          fetch(st + s + NB - 1, xa[(s + NB - 1) % NB], xb[(s + NB - 1) % NB]);
+          __builtin_amdgcn_sched_barrier(0);
+          compute(xa[s % NB], xb[s % NB]);
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < CH + NB - 1; ++s) {
+        if (st + s < full_steps) {
+          if (st + s + NB - 1 < full_steps)
+            fetch(st + s + NB - 1, xa[(s + NB - 1) % NB], xb[(s + NB - 1) % NB]);
+          __builtin_amdgcn_sched_barrier(0);
+          compute(xa[s % NB], xb[s % NB]);
+        }
+      }
+      // tail words, then the epilogue (below)
+      goto tail;
+    }
+  }
   if (full_steps > 0) fetch(0, a0, b0);
+  {
   int64_t st = 0;
   // sched_barrier(0) keeps the scheduler from sinking the loads below the MFMAs
   for (; st + 1 < full_steps; st += 2) {
@@ -238,6 +271,8 @@ __device__ __forceinline__ void tile(const uint64_t* __restrict__ A, int64_t lda
     compute(a1, b1);
   }
   if (st < full_steps) compute(a0, b0);
+  }
+tail:
   // Tail: words past the end of the row read as zero.
   {
     const int64_t w = full_steps * 2 * KV;

@@ -12,8 +12,9 @@ pytestmark = pytest.mark.gpu
 SEMIRINGS = [("gf2", oracle.GF2), ("bool", oracle.BOOLEAN)]
 LEAVES = [("valu", 1, 1), ("mfma128x64", 2, 1), ("mfma64x64", 2, 2), ("mfma64x128", 2, 3),
           ("mfma64x32", 2, 4), ("mfma_lds256", 2, 5), ("mfma_deep128x64", 2, 6),
+          ("mfma_chunk64x128", 2, 7),
           ("f4_128x64", 3, 1), ("f4_64x64", 3, 2), ("f4_64x128", 3, 3), ("f4_64x32", 3, 4),
-          ("f4_lds256", 3, 5), ("f4_deep128x64", 3, 6)]
+          ("f4_lds256", 3, 5), ("f4_deep128x64", 3, 6), ("f4_chunk64x128", 3, 7)]
 
 
 @pytest.fixture(scope="module")
@@ -64,7 +65,8 @@ def test_config1_2048_full(bmm, sname, sr, lname, leaf, tile):
 
 
 RAGGED = [(1, 1, 1), (1, 64, 1), (3, 65, 2), (33, 70, 65), (100, 300, 129), (257, 1000, 200),
-          (128, 4096, 64), (130, 129, 33), (64, 8192, 96), (300, 64, 300)]
+          (128, 4096, 64), (130, 129, 33), (64, 8192, 96), (300, 64, 300), (192, 6080, 160),
+          (70, 3840, 130)]
 
 
 @pytest.mark.parametrize("sname,sr", SEMIRINGS)
