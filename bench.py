@@ -25,10 +25,10 @@ PEAK_MFMA_F4_TOPS = 10100.0       # dense fp4 (E2M1) MFMA
 # * 2 bit operations (AND and XOR/OR) per fused v_bitop3_b32
 PEAK_VALU_FUSED_TBOPS = 5033.2
 # Bytes that one Boolean leaf launch at n = 2^18 moves between L2 and memory: rocprofv3
-# FETCH_SIZE and WRITE_SIZE of the int8 leaf with 64 x 128 tiles (the tuned tile), scaled
-# by the same counters on a 4 GiB copy in the same runs (reads x 2.0, writes x 1.0); see
-# profiles/pmc_traffic_leaf_boolean_n262144.md.  Valid for that kernel only.
-MEASURED_TRAFFIC = {("mfma", 3, 1 << 18): (8428913479.5 * 2.0 + 21601547.0) * 1024}
+# FETCH_SIZE and WRITE_SIZE of the int8 leaf with the tuned tile (7: 64 x 128, chunked
+# loop), scaled by the same counters on a 4 GiB copy in the same runs (reads x 2.0, writes
+# x 1.0); see profiles/pmc_traffic_leaf_boolean_n262144.md.  Valid for that kernel only.
+MEASURED_TRAFFIC = {("mfma", 7, 1 << 18): (9.48434e9 * 2.0 + 2.22841e7) * 1024}
 
 
 def log(*a):
@@ -104,7 +104,7 @@ def run_batched(args, torch, np, bmm, bmmgen):
     # every (leaf, tile) candidate timed once for the record, then the autotuner's choice
     cands = {}
     for lf, lname in [(bmm.LEAF_MFMA_I8, "int8"), (bmm.LEAF_MFMA_F4, "fp4")]:
-        for tl, tname in [(1, "128x64"), (2, "64x64")]:
+        for tl, tname in [(1, "128x64"), (2, "64x64"), (3, "64x128")]:
             pl = bmm.BatchedPlan(probs, options=bmm.Options(leaf=lf, tile=tl))
             pl.launch()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -169,7 +169,8 @@ def run_batched(args, torch, np, bmm, bmmgen):
         "one_launch_per_product_s": round(t_loop, 5),
         "one_launch_per_product_pbops": round(bops / t_loop / 1e15, 4),
         "speedup": round(t_loop / t_graph, 3), "verified_16_problems": ok,
-        "autotuned": {"leaf": {2: "int8", 3: "fp4"}[leaf], "tile": {1: "128x64", 2: "64x64"}[tile]},
+        "autotuned": {"leaf": {2: "int8", 3: "fp4"}[leaf],
+                      "tile": {1: "128x64", 2: "64x64", 3: "64x128"}[tile]},
         "candidates_s": cands,
         "frac_of_peak": round(bops / t_graph / 1e12 / (PEAK_MFMA_F4_TOPS if leaf == 3
                                                         else PEAK_MFMA_I8_TOPS), 4)}), flush=True)

@@ -19,14 +19,14 @@ namespace {
 
 struct Plan {
   BatchedDesc* descs = nullptr;  // device
-  uint32_t* begins = nullptr;    // device: first tile of each problem
-  unsigned int* counter = nullptr;
+  BatchedSeg* segs = nullptr;    // device: every queue's segments, queue after queue
+  unsigned int* counters = nullptr;
+  BatchedQueues queues{};
   int64_t count = 0;
-  int64_t total_tiles = 0;
   int grid = 0;
   int device = 0;
   int leaf = BMM_LEAF_MFMA_I8;  // BMM_LEAF_MFMA_I8 or BMM_LEAF_MFMA_F4
-  int tile = 2;                 // 1: 128 x 64 per wave, 2: 64 x 64
+  int tile = 2;                 // 1: 128 x 64 per wave, 2: 64 x 64, 3: 64 x 128
 };
 
 int validate_problem(const bmm_problem& p, int64_t i) {
@@ -78,17 +78,20 @@ int build_plan(const bmm_problem* problems, int64_t count, const bmm_options* op
   if (tile <= 0) tile = 2;
   if (leaf != BMM_LEAF_MFMA_I8 && leaf != BMM_LEAF_MFMA_F4)
     return bfail(BMM_E_UNSUPPORTED, "batched plans run the int8 or fp4 matrix-core leaf");
-  if (tile != 1 && tile != 2) return bfail(BMM_E_INVAL, "batched tile must be 1 or 2");
+  if (tile < 1 || tile > 3) return bfail(BMM_E_INVAL, "batched tile must be 1, 2 or 3");
   if (leaf == BMM_LEAF_MFMA_F4 && kmax >= ((int64_t)1 << 24))
     return bfail(BMM_E_UNSUPPORTED, "the fp4 leaf counts exactly only for k < 2^24");
   if (kmax >= ((int64_t)1 << 31))
     return bfail(BMM_E_UNSUPPORTED, "the int8 leaf counts exactly only for k < 2^31");
+  // longest k first, so the queues drain with short items at the end
   std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
     return problems[a].k > problems[b].k;
   });
   const int TR = batched_tile_rows(tile), TC = batched_tile_cols(tile);
   std::vector<BatchedDesc> host;
-  int64_t tiles = 0;
+  std::vector<BatchedSeg> qsegs[kXcds];
+  uint64_t qitems[kXcds] = {};
+  int rot = 0;
   for (int64_t i : order) {
     const bmm_problem& p = problems[i];
     BatchedDesc d;
@@ -101,41 +104,69 @@ int build_plan(const bmm_problem* problems, int64_t count, const bmm_options* op
     d.m = p.m;
     d.k = p.k;
     d.n = p.n;
-    d.tile_begin = tiles;
     d.semiring = p.semiring;
-    d.tiles_n = (int32_t)((p.n + TC - 1) / TC);
-    tiles += ((p.m + TR - 1) / TR) * d.tiles_n;
+    d.aligned = ((((uintptr_t)p.A | (uintptr_t)p.B) & 15) == 0 && ((p.lda | p.ldb) & 1) == 0) ? 1 : 0;
+    // wave tiles cover whole 64-bit words of C, so padding bits are written (as zero)
+    const int64_t tiles_m = (p.m + TR - 1) / TR;
+    const int64_t tiles_n = (((p.n + 63) / 64) * 64 + TC - 1) / TC;
+    const int64_t items_m = (tiles_m + 1) / 2, items_n = (tiles_n + 1) / 2;
+    if (tiles_m >= ((int64_t)1 << 31) || tiles_n >= ((int64_t)1 << 31))
+      return bfail(BMM_E_UNSUPPORTED, "problem %ld: too many tiles", (long)i);
+    d.tiles_m = (int32_t)tiles_m;
+    d.tiles_n = (int32_t)tiles_n;
+    d.items_m = (int32_t)items_m;
+    d.items_n = (int32_t)items_n;
+    const uint32_t pi = (uint32_t)host.size();
     host.push_back(d);
+    // the problem's items, in banded order, split into contiguous ranges over the
+    // queues; the odd items left over rotate from problem to problem
+    const uint64_t items = (uint64_t)items_m * (uint64_t)items_n;
+    const uint64_t base = items / kXcds, rem = items % kXcds;
+    uint64_t lo = 0;
+    for (int xi = 0; xi < kXcds; ++xi) {
+      const uint64_t sz = base + ((uint64_t)xi < rem ? 1 : 0);
+      if (sz == 0) continue;
+      const int x = (rot + xi) % kXcds;
+      qsegs[x].push_back(BatchedSeg{(uint32_t)qitems[x], pi, (uint32_t)lo, 0u});
+      qitems[x] += sz;
+      lo += sz;
+    }
+    rot = (int)((rot + rem) % kXcds);
   }
-  if (tiles >= ((int64_t)1 << 32) - ((int64_t)1 << 20))
-    return bfail(BMM_E_UNSUPPORTED, "batched plans hold fewer than 2^32 tiles (%ld)", (long)tiles);
   Plan P;
   P.leaf = leaf;
   P.tile = tile;
   P.count = (int64_t)host.size();
-  P.total_tiles = tiles;
-  std::vector<uint32_t> begins;
-  for (const auto& d : host) begins.push_back((uint32_t)d.tile_begin);
+  std::vector<BatchedSeg> segs;
+  for (int x = 0; x < kXcds; ++x) {
+    if (qitems[x] >= ((uint64_t)1 << 32) - ((uint64_t)1 << 20))
+      return bfail(BMM_E_UNSUPPORTED, "batched plans hold fewer than 2^32 items per queue");
+    P.queues.seg_off[x] = (uint32_t)segs.size();
+    P.queues.seg_count[x] = (uint32_t)qsegs[x].size();
+    P.queues.items[x] = (uint32_t)qitems[x];
+    segs.insert(segs.end(), qsegs[x].begin(), qsegs[x].end());
+  }
   if (hipGetDevice(&P.device) != hipSuccess) return bfail(BMM_E_DEVICE, "hipGetDevice");
   int cus = 256;
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, P.device);
-  P.grid = std::max(1, cus * wg_per_cu);
+  P.grid = std::max(kXcds, cus * wg_per_cu);
   if (P.count > 0) {
+    const size_t cbytes = sizeof(unsigned int) * kXcds * kBatchedCounterStride;
     if (hipMalloc((void**)&P.descs, sizeof(BatchedDesc) * host.size()) != hipSuccess ||
-        hipMalloc((void**)&P.begins, sizeof(uint32_t) * begins.size()) != hipSuccess ||
-        hipMalloc((void**)&P.counter, 256) != hipSuccess) {
+        hipMalloc((void**)&P.segs, sizeof(BatchedSeg) * segs.size()) != hipSuccess ||
+        hipMalloc((void**)&P.counters, cbytes) != hipSuccess) {
       (void)hipGetLastError();
       (void)hipFree(P.descs);
-      (void)hipFree(P.begins);
+      (void)hipFree(P.segs);
       return bfail(BMM_E_NOMEM, "plan allocation");
     }
     if (hipMemcpy(P.descs, host.data(), sizeof(BatchedDesc) * host.size(),
                   hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(P.begins, begins.data(), sizeof(uint32_t) * begins.size(),
+        hipMemcpy(P.segs, segs.data(), sizeof(BatchedSeg) * segs.size(),
                   hipMemcpyHostToDevice) != hipSuccess) {
       (void)hipFree(P.descs);
-      (void)hipFree(P.begins);
-      (void)hipFree(P.counter);
+      (void)hipFree(P.segs);
+      (void)hipFree(P.counters);
       return bfail(BMM_E_DEVICE, "plan upload: %s", hipGetErrorString(hipGetLastError()));
     }
   }
@@ -163,8 +194,9 @@ int bmm_batched_plan_create(const bmm_problem* problems, int64_t count,
 int bmm_batched_plan_launch(void* plan, void* hip_stream) {
   if (!plan) return bfail(BMM_E_INVAL, "null plan");
   Plan* P = static_cast<Plan*>(plan);
+  if (P->count == 0) return BMM_OK;
   hipError_t e = launch_batched_persistent(
-      P->descs, P->begins, P->count, P->total_tiles, P->counter, P->grid, P->tile,
+      P->descs, P->segs, P->queues, P->counters, P->grid, P->tile,
       P->leaf == BMM_LEAF_MFMA_F4 ? 1 : 0, (hipStream_t)hip_stream);
   if (e != hipSuccess) return bfail(BMM_E_DEVICE, "batched launch: %s", hipGetErrorString(e));
   return BMM_OK;
@@ -173,14 +205,14 @@ int bmm_batched_plan_launch(void* plan, void* hip_stream) {
 void bmm_batched_plan_destroy(void* plan) {
   if (!plan) return;
   Plan* P = static_cast<Plan*>(plan);
-  if (P->descs || P->counter) {
+  if (P->descs || P->counters) {
     int cur = 0;
     (void)hipGetDevice(&cur);
     (void)hipSetDevice(P->device);
     (void)hipDeviceSynchronize();
     (void)hipFree(P->descs);
-    (void)hipFree(P->begins);
-    (void)hipFree(P->counter);
+    (void)hipFree(P->segs);
+    (void)hipFree(P->counters);
     (void)hipSetDevice(cur);
   }
   delete P;
@@ -197,8 +229,8 @@ int bmm_autotune_batched(const bmm_problem* problems, int64_t count, int* leaf_o
   double best = 1e30;
   int best_leaf = BMM_LEAF_MFMA_I8, best_tile = 2, best_wpc = 4, rc = BMM_OK;
   for (int leaf : {BMM_LEAF_MFMA_I8, BMM_LEAF_MFMA_F4}) {
-    for (int tile : {1, 2}) {
-      for (int wpc : {2, 4, 8}) {
+    for (int tile : {1, 2, 3}) {
+      for (int wpc : {2, 4}) {
         bmm_options o;
         bmm_options_init(&o);
         o.leaf = leaf;

@@ -42,6 +42,18 @@ struct TileCoord {
   int64_t b, tm, tn;
 };
 
+// Banded order of a grid_m x grid_n tile grid: bands of kGroupRows tile rows,
+// each walked column by column, so consecutive tiles share operand panels.
+__device__ __forceinline__ void band_coord(int64_t r, int64_t grid_m, int64_t grid_n,
+                                           int64_t& tm, int64_t& tn) {
+  const int64_t band = (int64_t)kGroupRows * grid_n;
+  const int64_t first = (r / band) * kGroupRows;
+  const int64_t rows = grid_m - first < kGroupRows ? grid_m - first : kGroupRows;
+  const int64_t q = r - (r / band) * band;
+  tm = first + q % rows;
+  tn = q / rows;
+}
+
 __device__ __forceinline__ TileCoord xcd_tile(int64_t g, int64_t total, int64_t grid_m,
                                               int64_t grid_n) {
   const int64_t x = g % kXcds, j = g / kXcds;
@@ -50,13 +62,7 @@ __device__ __forceinline__ TileCoord xcd_tile(int64_t g, int64_t total, int64_t 
   const int64_t per_item = grid_m * grid_n;
   TileCoord c;
   c.b = t / per_item;
-  const int64_t r = t - c.b * per_item;
-  const int64_t band = (int64_t)kGroupRows * grid_n;
-  const int64_t first = (r / band) * kGroupRows;
-  const int64_t rows = grid_m - first < kGroupRows ? grid_m - first : kGroupRows;
-  const int64_t q = r - (r / band) * band;
-  c.tm = first + q % rows;
-  c.tn = q / rows;
+  band_coord(t - c.b * per_item, grid_m, grid_n, c.tm, c.tn);
   return c;
 }
 
@@ -124,22 +130,36 @@ hipError_t launch_random(uint64_t* dst, int64_t words, uint64_t seed, hipStream_
 // Zero a rows x words matrix (a fill kernel, safe under graph capture).
 hipError_t launch_zero(uint64_t* dst, int64_t ld, int64_t rows, int64_t words, hipStream_t s);
 
-// Persistent batched leaf over a device-resident problem table.
+// Persistent batched leaf over a device-resident problem table.  A work item is
+// one workgroup's 2 x 2 wave tiles of one problem; a problem's items, in banded
+// order, are split into contiguous ranges over kXcds queues (one per XCD), and
+// a queue's items are listed as segments (problem, first item) at increasing
+// queue positions.
 struct BatchedDesc {
   const uint64_t* A;
   const uint64_t* BT;
   uint64_t* C;
   int64_t lda, ldbt, ldc;
   int64_t m, k, n;
-  int64_t tile_begin;  // prefix sum of tiles over problems
-  int32_t semiring, tiles_n;
+  int32_t semiring;
+  int32_t aligned;           // A, B^T 16-byte aligned with even pitches: 16-byte loads
+  int32_t tiles_m, tiles_n;  // wave tiles (tiles_n covers C's padding words)
+  int32_t items_m, items_n;  // work items (2 x 2 wave tiles)
 };
-// begins[i] = descs[i].tile_begin as uint32 (total tiles < 2^32); cached in LDS
-// by every workgroup when count <= kBatchedLdsProblems.
-constexpr int64_t kBatchedLdsProblems = 16384;
-// tile 1: 128 x 64 per wave, 2: 64 x 64; fmt: mfma::MfmaFormat (0 int8, 1 E2M1).
-hipError_t launch_batched_persistent(const BatchedDesc* descs, const uint32_t* begins,
-                                     int64_t count, int64_t total_tiles, unsigned int* counter,
+struct BatchedSeg {
+  uint32_t begin;    // queue position of the segment's first item
+  uint32_t problem;  // index into the problem table
+  uint32_t item_lo;  // the problem's item at that position
+  uint32_t pad;
+};
+struct BatchedQueues {
+  uint32_t seg_off[kXcds], seg_count[kXcds], items[kXcds];
+};
+constexpr int kBatchedCounterStride = 64;  // uint32s between queue counters (256 bytes)
+// tile 1: 128 x 64 per wave, 2: 64 x 64, 3: 64 x 128; fmt: mfma::MfmaFormat (0 int8, 1 E2M1).
+// counters: kXcds * kBatchedCounterStride uint32s, zeroed by the launch itself.
+hipError_t launch_batched_persistent(const BatchedDesc* descs, const BatchedSeg* segs,
+                                     const BatchedQueues& queues, unsigned int* counters,
                                      int grid, int tile, int fmt, hipStream_t s);
 int batched_tile_rows(int tile);
 int batched_tile_cols(int tile);

@@ -18,6 +18,18 @@ typedef float v16f __attribute__((ext_vector_type(16)));
 // is 0.25 and the fp32 accumulator holds count / 4 exactly while k < 2^24.
 enum MfmaFormat { FMT_I8 = 0, FMT_F4 = 1 };
 
+// Semiring template value meaning "given at run time": the main loop does not
+// depend on the semiring (both feed exact 0/1 operands), only the epilogue's
+// reduction does, so one kernel can serve both with a single copy of the loop.
+constexpr int SEMI_ANY = -1;
+
+// Operands and results live in device (global) memory.  Pointers typed so keep
+// the loads and stores global even where the compiler cannot infer it (pointers
+// read from a problem table in memory would otherwise become generic accesses).
+#define BMM_GLOBAL __attribute__((address_space(1)))
+typedef const BMM_GLOBAL uint64_t* gq_ptr;
+typedef BMM_GLOBAL uint32_t* gd_ptr;
+
 template <int FMT>
 struct Acc;
 template <>
@@ -96,12 +108,14 @@ __device__ __forceinline__ void mfma_word(const uint64_t (&xa)[RA], const uint64
 template <int SEMI, int RA, int RB, int FMT>
 __device__ __forceinline__ void epilogue(const typename Acc<FMT>::type (&acc)[RA][RB],
                                          uint64_t* __restrict__ Cm, int64_t ldc, int64_t m,
-                                         int64_t n, int64_t tm, int64_t tn, int accumulate) {
+                                         int64_t n, int64_t tm, int64_t tn, int accumulate,
+                                         int semiring = SEMI) {
   constexpr int TM = 32 * RA, TN = 32 * RB;
+  const bool gf2 = SEMI == SEMI_ANY ? semiring == GF2 : SEMI == GF2;
   const int lane = threadIdx.x & 63;
   const int half = lane >> 5;
   const int li = lane & 31;
-  uint32_t* C32 = reinterpret_cast<uint32_t*>(Cm);
+  const gd_ptr C32 = (gd_ptr)Cm;
   const int64_t ldc32 = 2 * ldc;
   const int64_t n_words32 = ((n + 63) >> 6) * 2;  // dwords per C row incl. padding
   const int myv = ((li >> 3) << 2) | (li & 3);
@@ -123,7 +137,7 @@ __device__ __forceinline__ void epilogue(const typename Acc<FMT>::type (&acc)[RA
           cnt = __float2int_rn(acc[f][g][v] * 4.0f);  // exact: a multiple of 0.25
         else
           cnt = acc[f][g][v];
-        const bool bit = (SEMI == GF2) ? ((cnt & 1) != 0) : (cnt != 0);
+        const bool bit = gf2 ? ((cnt & 1) != 0) : (cnt != 0);
         const uint64_t bal = __ballot(bit);
         const uint32_t word = myhi ? (uint32_t)(bal >> 32) : (uint32_t)bal;
         mine = (myv == v) ? word : mine;
@@ -131,8 +145,8 @@ __device__ __forceinline__ void epilogue(const typename Acc<FMT>::type (&acc)[RA
       mine &= cmask;
       const int64_t row = tm * TM + 32 * f + li;
       if (half == 0 && row < m) {
-        uint32_t* dst = C32 + row * ldc32 + cw;
-        if (accumulate) mine = (SEMI == GF2) ? (mine ^ *dst) : (mine | *dst);
+        const gd_ptr dst = C32 + row * ldc32 + cw;
+        if (accumulate) mine = gf2 ? (mine ^ *dst) : (mine | *dst);
         *dst = mine;
       }
     }
@@ -150,26 +164,26 @@ __device__ __forceinline__ void tile(const uint64_t* __restrict__ A, int64_t lda
                                      const uint64_t* __restrict__ BT, int64_t ldbt,
                                      uint64_t* __restrict__ Cm, int64_t ldc, int64_t m,
                                      int64_t k, int64_t n, int64_t tm, int64_t tn,
-                                     int accumulate) {
+                                     int accumulate, int semiring = SEMI) {
   constexpr int TM = 32 * RA, TN = 32 * RB;
   const int lane = threadIdx.x & 63;
   const int half = lane >> 5;
   const int li = lane & 31;
   const int64_t kw = (k + 63) >> 6;
 
-  const uint64_t* arow[RA];
-  const uint64_t* brow[RB];
+  gq_ptr arow[RA];
+  gq_ptr brow[RB];
 #pragma unroll
   for (int f = 0; f < RA; ++f) {
     int64_t r = tm * TM + 32 * f + li;
     r = r < m ? r : m - 1;
-    arow[f] = A + r * lda + KV * half;
+    arow[f] = (gq_ptr)A + r * lda + KV * half;
   }
 #pragma unroll
   for (int g = 0; g < RB; ++g) {
     int64_t c = tn * TN + 32 * g + li;
     c = c < n ? c : n - 1;
-    brow[g] = BT + c * ldbt + KV * half;
+    brow[g] = (gq_ptr)BT + c * ldbt + KV * half;
   }
 
   using AccV = typename Acc<FMT>::type;
@@ -191,13 +205,13 @@ __device__ __forceinline__ void tile(const uint64_t* __restrict__ A, int64_t lda
     if constexpr (KV == 2) {
 #pragma unroll
       for (int f = 0; f < RA; ++f) {
-        const ulonglong2 v = *reinterpret_cast<const ulonglong2*>(arow[f] + w);
+        const ulonglong2 v = *reinterpret_cast<const ulonglong2*>((const uint64_t*)(arow[f] + w));
         xa[0][f] = v.x;
         xa[1][f] = v.y;
       }
 #pragma unroll
       for (int g = 0; g < RB; ++g) {
-        const ulonglong2 v = *reinterpret_cast<const ulonglong2*>(brow[g] + w);
+        const ulonglong2 v = *reinterpret_cast<const ulonglong2*>((const uint64_t*)(brow[g] + w));
         xb[0][g] = v.x;
         xb[1][g] = v.y;
       }
@@ -223,7 +237,7 @@ __device__ __forceinline__ void tile(const uint64_t* __restrict__ A, int64_t lda
       __builtin_amdgcn_sched_barrier(0);
       compute(xa[s % NB], xb[s % NB]);
     }
-    epilogue<SEMI, RA, RB, FMT>(acc, Cm, ldc, m, n, tm, tn, accumulate);
+    epilogue<SEMI, RA, RB, FMT>(acc, Cm, ldc, m, n, tm, tn, accumulate, semiring);
     return;
   }
   if constexpr (STEPS < 0) {
@@ -290,7 +304,7 @@ tail:
     }
   }
 
-  epilogue<SEMI, RA, RB, FMT>(acc, Cm, ldc, m, n, tm, tn, accumulate);
+  epilogue<SEMI, RA, RB, FMT>(acc, Cm, ldc, m, n, tm, tn, accumulate, semiring);
 }
 
 }  // namespace mfma

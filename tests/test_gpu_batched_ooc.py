@@ -59,20 +59,53 @@ def test_batched_mixed(bmm, transposed):
 
 
 @pytest.mark.parametrize("leaf", [2, 3])
-@pytest.mark.parametrize("tile", [1, 2])
+@pytest.mark.parametrize("tile", [1, 2, 3])
 def test_batched_leaf_and_tile(bmm, leaf, tile):
-    """Every batched leaf kind (int8, fp4) and tile (128 x 64, 64 x 64)."""
-    probs, host = make_problems(36, 50 + 2 * leaf + tile)
+    """Every batched leaf kind (int8, fp4) and tile (128 x 64, 64 x 64, 64 x 128)."""
+    probs, host = make_problems(36, 50 + 3 * leaf + tile)
     announce("batched leaf/tile", leaf, tile)
     bmm.bmm_batched(probs, options=bmm.Options(leaf=leaf, tile=tile))
     check(probs, host)
+
+
+@pytest.fixture(scope="module")
+def large_batch():
+    """Ten problems of 500-2100 rows and columns and 3000-6100 bits of k: every
+    problem spans many work items, split over several queues, and most reach the
+    chunked long-k loop; odd word counts of k take the 8-byte-load path."""
+    rng = np.random.default_rng(2024)
+    seed = 77
+    items = []
+    for p in range(10):
+        m, n = (int(x) for x in rng.integers(500, 2100, size=2))
+        k = int(rng.integers(3000, 6100))
+        sr = oracle.GF2 if p % 2 == 0 else oracle.BOOLEAN
+        dist = bmmgen.Dist.half() if sr == oracle.GF2 else bmmgen.Dist.inv_sqrt(k)
+        A = bmmgen.fill_cpu(m, k, seed, bmmgen.batched_tag(p, "A"), dist)
+        B = bmmgen.fill_cpu(k, n, seed, bmmgen.batched_tag(p, "B"), dist)
+        items.append((sr, A, B, m, k, n, oracle.mul(A, B, k, n, sr)))
+    return items
+
+
+@pytest.mark.parametrize("leaf", [2, 3])
+@pytest.mark.parametrize("tile", [1, 2, 3])
+def test_batched_large_items(bmm, large_batch, leaf, tile):
+    probs = []
+    for sr, A, B, m, k, n, _ in large_batch:
+        probs.append(dict(semiring=sr, m=m, k=k, n=n, A=to_dev(A),
+                          B=to_dev(transpose_packed(B, k, n)),
+                          C=empty_dev(m, words(n), fill=-1), b_transposed=True))
+    announce("batched large items", leaf, tile)
+    bmm.bmm_batched(probs, options=bmm.Options(leaf=leaf, tile=tile))
+    for pr, (sr, A, B, m, k, n, want) in zip(probs, large_batch):
+        assert np.array_equal(from_dev(pr["C"], words(n)), want), (sr, m, k, n, leaf, tile)
 
 
 def test_batched_autotune_and_auto_plan(bmm):
     probs, host = make_problems(24, 99)
     announce("batched autotune")
     leaf, tile, secs = bmm.bmm_autotune_batched(probs)
-    assert leaf in (2, 3) and tile in (1, 2) and secs > 0
+    assert leaf in (2, 3) and tile in (1, 2, 3) and secs > 0
     check(probs, host)
     for pr in probs:
         pr["C"].fill_(-1)
