@@ -149,11 +149,15 @@ void pick_leaf(int semiring, int64_t m, int64_t k, int64_t n, int64_t batch,
   }
   if (*leaf == BMM_LEAF_AUTO) *leaf = BMM_LEAF_MFMA_I8;
   if (*tile <= 0) {
-    // default MFMA tile: 128 x 64 per wave; when that gives fewer than 16 waves per
-    // CU over the whole launch, 64 x 64 tiles fill the chip better
-    *tile = 1;
+    // default MFMA tile for shapes the table lacks, from the gfx950 timings: when 128 x 64
+    // wave tiles give fewer than 16 waves per CU over the whole launch, 64 x 64 tiles fill
+    // the chip better; long k runs int8 on 64 x 128 wave tiles in the chunked loop (tile 7)
+    // and fp4 LDS-staged (tile 5); everything else 128 x 64 per wave
     const int64_t waves = batch * ((m + 127) / 128) * ((n + 63) / 64);
     if (*leaf != BMM_LEAF_VALU && waves < 4096) *tile = 2;
+    else if (*leaf == BMM_LEAF_MFMA_I8 && k >= 8192) *tile = 7;
+    else if (*leaf == BMM_LEAF_MFMA_F4 && k >= 4096) *tile = 5;
+    else *tile = 1;
   }
 }
 

@@ -113,7 +113,8 @@ def test_autotune_table_roundtrip(tmp_path):
 
 def test_leaf_choice_follows_the_table(tmp_path):
     """bmm_leaf_choice is host-only: explicit options win, then the table, then the
-    default rule (128 x 64 tiles, 64 x 64 when the launch has fewer than 4096 waves)."""
+    default rule (64 x 64 tiles when the launch has fewer than 4096 waves of 128 x 64;
+    else for k >= 8192 int8 tile 7, for k >= 4096 fp4 tile 5; else 128 x 64)."""
     import paper_1909_01554_amd as bmm
     p = tmp_path / "t.txt"
     p.write_text("leaf 1 4096 8192 4096 1 3 1 4 5\n")
@@ -122,7 +123,12 @@ def test_leaf_choice_follows_the_table(tmp_path):
     assert bmm.bmm_leaf_choice(bmm.BOOLEAN, 4096, 8192, 4096, options=bmm.Options(leaf=2)) == (2, 4)
     assert bmm.bmm_leaf_choice(bmm.BOOLEAN, 4096, 8192, 4096,
                                options=bmm.Options(leaf=2, tile=3)) == (2, 3)
-    assert bmm.bmm_leaf_choice(bmm.GF2, 1 << 16, 1 << 16, 1 << 16) == (2, 1)
+    assert bmm.bmm_leaf_choice(bmm.GF2, 1 << 16, 1 << 16, 1 << 16) == (2, 7)
+    assert bmm.bmm_leaf_choice(bmm.GF2, 1 << 16, 1 << 16, 1 << 16,
+                               options=bmm.Options(leaf=3)) == (3, 5)
+    assert bmm.bmm_leaf_choice(bmm.GF2, 1 << 16, 4096, 1 << 16) == (2, 1)
+    assert bmm.bmm_leaf_choice(bmm.GF2, 1 << 16, 2048, 1 << 16,
+                               options=bmm.Options(leaf=3)) == (3, 1)
     assert bmm.bmm_leaf_choice(bmm.GF2, 256, 256, 256) == (2, 2)
     with pytest.raises(bmm.BmmError):
         bmm.bmm_leaf_choice(7, 1, 1, 1)
