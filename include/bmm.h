@@ -122,7 +122,8 @@ int bmm_boolean(const uint64_t* A, int64_t lda, const uint64_t* B, int64_t ldb, 
  * self-inverse alternative basis, section 2.2; also the chaining alternative
  * basis, section 2.3, and standard-basis Strassen-Winograd, section 2.1) with
  * `depth` levels of 2 x 2 blocks above a cubic leaf (depth -1 = autotuned;
- * 0 = cubic).
+ * shapes the table lacks take the largest depth whose leaves keep every
+ * dimension >= 2048 bits, at most 8; 0 = cubic).
  * Requires m % 2^depth == 0, k % (64 * 2^depth) == 0 and n % (64 * 2^depth) == 0,
  * else BMM_E_UNSUPPORTED.  The workspace (device memory, >= the size from
  * bmm_gf2_strassen_workspace for the same arguments) holds the basis-changed

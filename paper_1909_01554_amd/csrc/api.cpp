@@ -274,13 +274,14 @@ int make_plan(int64_t m, int64_t k, int64_t n, int depth, const bmm_options& o, 
     }
   }
   if (depth == -1) {
-    // largest depth keeping every leaf dimension >= 4096 bits (at most 8 levels)
+    // largest depth keeping every leaf dimension >= 2048 bits (at most 8 levels): the
+    // depth tuner's optimum at n = 2^18 on gfx950 has 2048-bit leaves
     depth = 0;
     while (depth < 8) {
       const int d = depth + 1;
       const int64_t u = (int64_t)1 << d;
       if (m % u || k % (64 * u) || n % (64 * u)) break;
-      if (m / u < 4096 || k / u < 4096 || n / u < 4096) break;
+      if (m / u < 2048 || k / u < 2048 || n / u < 2048) break;
       depth = d;
     }
   }
@@ -554,6 +555,11 @@ bool batched_tuned(int64_t count, double ops, int* leaf, int* tile, int* wg_per_
 void batched_tune_set(int64_t count, double ops, int leaf, int tile, int wg_per_cu) {
   std::lock_guard<std::mutex> lock(g_mu);
   g_batched[{count, ops_bucket(ops)}] = {leaf, tile, wg_per_cu};
+}
+
+void choose_leaf(int semiring, int64_t m, int64_t k, int64_t n, int64_t batch,
+                 const bmm_options& o, int* leaf, int* tile) {
+  pick_leaf(semiring, m, k, n, batch, o, leaf, tile);
 }
 
 hipError_t to_alt_basis(uint64_t* C, int64_t ldc, int64_t rows, int64_t words, int depth,

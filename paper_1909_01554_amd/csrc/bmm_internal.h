@@ -177,6 +177,10 @@ void batched_tune_set(int64_t count, double ops, int leaf, int tile, int wg_per_
 namespace bmm {
 
 // Inverse of the result's basis change of a scheme (standard -> alternative basis).
+// Leaf kind and tile of a product (options, then the autotune table, then the
+// default rule), as every entry point chooses them.
+void choose_leaf(int semiring, int64_t m, int64_t k, int64_t n, int64_t batch,
+                 const bmm_options& o, int* leaf, int* tile);
 hipError_t to_alt_basis(uint64_t* C, int64_t ldc, int64_t rows, int64_t words, int depth,
                         int scheme, hipStream_t s);
 

@@ -302,7 +302,14 @@ extern "C" int bmm_ooc(int semiring, const uint64_t* A, int64_t lda, const uint6
   if (leaf < BMM_LEAF_VALU || leaf > BMM_LEAF_MFMA_F4) return ofail(BMM_E_INVAL, "unknown leaf");
   if (leaf == BMM_LEAF_MFMA_F4 && std::min(block, k) >= ((int64_t)1 << 24))
     return ofail(BMM_E_UNSUPPORTED, "the fp4 leaf counts exactly only for k < 2^24");
-  int tile = o.tile > 0 ? o.tile : 1;
+  // the cubic block products take the tile any product of their shape would take
+  int tile = o.tile;
+  {
+    bmm_options q = o;
+    q.leaf = leaf;
+    int lf = leaf;
+    choose_leaf(semiring, bm, bk, bn, 1, q, &lf, &tile);
+  }
 
   const auto t0 = std::chrono::steady_clock::now();
   if (semiring == BMM_GF2 && !(o.flags & BMM_FLAG_OOC_BLOCK_ORDER) &&
