@@ -26,9 +26,10 @@ PEAK_MFMA_F4_TOPS = 10100.0       # dense fp4 (E2M1) MFMA
 PEAK_VALU_FUSED_TBOPS = 5033.2
 # Bytes that one Boolean leaf launch at n = 2^18 moves between L2 and memory: rocprofv3
 # FETCH_SIZE and WRITE_SIZE of the int8 leaf with the tuned tile (7: 64 x 128, chunked
-# loop), scaled by the same counters on a 4 GiB copy in the same runs (reads x 2.0, writes
-# x 1.0); see profiles/pmc_traffic_leaf_boolean_n262144.md.  Valid for that kernel only.
-MEASURED_TRAFFIC = {("mfma", 7, 1 << 18): (9.48434e9 * 2.0 + 2.22841e7) * 1024}
+# loop, wide operand expansion), scaled by the same counters on a 4 GiB copy in the same
+# runs (reads x 2.0, writes x 1.0); see profiles/pmc_traffic_leaf_boolean_n262144.md.
+# Valid for that kernel only.
+MEASURED_TRAFFIC = {("mfma", 7, 1 << 18): (1.1294e10 * 2.0 + 6.88363e7) * 1024}
 
 
 def log(*a):

@@ -69,6 +69,10 @@ __device__ __forceinline__ void resolve_item(const BatchedSeg* __restrict__ segs
   }
 }
 
+// The 32-bit operand expansion: the persistent loop's own state leaves no room
+// for the wide form's registers.
+constexpr bool kWide = false;
+
 template <int RA, int RB, int FMT>
 __device__ __forceinline__ void run_item(const BatchedDesc& d, int64_t item, int w) {
   int64_t im, in;
@@ -83,11 +87,11 @@ __device__ __forceinline__ void run_item(const BatchedDesc& d, int64_t item, int
   // (the chunked long-k loop of the one-shot leaf measured no faster here: most
   // items are short, and its code doubles the kernel)
   if (d.aligned) {
-    mfma::tile<mfma::SEMI_ANY, RA, RB, 2, FMT>(A, d.lda, BT, d.ldbt, C, d.ldc, d.m, d.k, d.n, tm,
-                                               tn, 0, d.semiring);
+    mfma::tile<mfma::SEMI_ANY, RA, RB, 2, FMT, 2, 0, kWide>(A, d.lda, BT, d.ldbt, C, d.ldc, d.m,
+                                                          d.k, d.n, tm, tn, 0, d.semiring);
   } else {
-    mfma::tile<mfma::SEMI_ANY, RA, RB, 1, FMT>(A, d.lda, BT, d.ldbt, C, d.ldc, d.m, d.k, d.n, tm,
-                                               tn, 0, d.semiring);
+    mfma::tile<mfma::SEMI_ANY, RA, RB, 1, FMT, 2, 0, kWide>(A, d.lda, BT, d.ldbt, C, d.ldc, d.m,
+                                                          d.k, d.n, tm, tn, 0, d.semiring);
   }
 }
 

@@ -12,7 +12,7 @@
 // registers.  The order of k inside a dot product is free as long as A and B
 // use the same one, so a 32-bit half x of a word yields the eight dwords
 // (x >> d) & 0x01010101 (d = 0..7): byte e of dword d is bit 8e + d of x, 0 or
-// 1.  GF(2) parity alone would only need the low bit of each byte, but
+// 1 (for one side of the tile both halves at once, from a 64-bit shift).  GF(2) parity alone would only need the low bit of each byte, but
 // operand bytes holding the other random bits too make the matrix cores
 // switch far more on dense inputs and run at a lower rate, so both semirings
 // feed exact 0/1 bytes.
@@ -27,7 +27,7 @@ namespace bmm {
 namespace {
 
 // Each workgroup owns 2 x 2 wave tiles; workgroups are ordered for L2 reuse per XCD.
-template <int SEMI, int RA, int RB, int KV, int FMT, int NB = 2, int STEPS = 0>
+template <int SEMI, int RA, int RB, int KV, int FMT, int NB = 2, int STEPS = 0, bool WIDE = true>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void leaf_mfma_kernel(
     LeafBatch p, int64_t tiles_m, int64_t tiles_n) {
   const int64_t grid_m = (tiles_m + 1) >> 1, grid_n = (tiles_n + 1) >> 1;
@@ -37,13 +37,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void l
   const int64_t tn = 2 * c.tn + (w & 1);
   if (c.b >= p.batch || tm >= tiles_m || tn >= tiles_n) return;  // uniform per wave
   const int64_t b = c.b;
-  mfma::tile<SEMI, RA, RB, KV, FMT, NB, STEPS>(p.A + b * p.strideA, p.lda, p.BT + b * p.strideB, p.ldbt,
+  mfma::tile<SEMI, RA, RB, KV, FMT, NB, STEPS, WIDE>(p.A + b * p.strideA, p.lda, p.BT + b * p.strideB, p.ldbt,
                                     p.C + b * p.strideC, p.ldc, p.m, p.k, p.n, tm, tn,
                                     p.accumulate);
 }
 
 // DEEP: int8 leaves of the recursion's lengths (k = 2048 or 4096 bits, 16-byte
-// aligned) run a fully unrolled 3-deep load pipeline.  CHUNKED: aligned int8 leaves
+// aligned) run a fully unrolled 3-deep load pipeline (with the 32-bit operand
+// expansion: the wide one measured no faster there and spills in its prologue).  CHUNKED: aligned int8 leaves
 // run the 2-deep pipeline as a loop over fully unrolled chunks of 12 steps, which
 // leaves the compiler's conservative wait for outstanding loads at the loop's
 // back edge once per chunk instead of once per step pair.  All else takes the
@@ -62,12 +63,12 @@ hipError_t launch_t(const LeafBatch& p, hipStream_t s) {
   // the unrolled pipelines are built for the int8 format only (fp4 operands spill)
   if constexpr (DEEP && FMT == mfma::FMT_I8) {
     if (aligned16 && p.k == 2048) {
-      hipLaunchKernelGGL((leaf_mfma_kernel<SEMI, RA, RB, 2, FMT, 3, 8>), g, b, 0, s, p, tiles_m,
+      hipLaunchKernelGGL((leaf_mfma_kernel<SEMI, RA, RB, 2, FMT, 3, 8, false>), g, b, 0, s, p, tiles_m,
                          tiles_n);
       return hipGetLastError();
     }
     if (aligned16 && p.k == 4096) {
-      hipLaunchKernelGGL((leaf_mfma_kernel<SEMI, RA, RB, 2, FMT, 3, 16>), g, b, 0, s, p, tiles_m,
+      hipLaunchKernelGGL((leaf_mfma_kernel<SEMI, RA, RB, 2, FMT, 3, 16, false>), g, b, 0, s, p, tiles_m,
                          tiles_n);
       return hipGetLastError();
     }

@@ -63,7 +63,8 @@ __device__ __forceinline__ v4i expand4(uint32_t x, int first) {
   return o;
 }
 
-template <int SEMI, int RA, int RB, int FMT>
+// WIDE: expand the rows of the tile's longer side with 64-bit shifts (below).
+template <int SEMI, int RA, int RB, int FMT, bool WIDE = true>
 __device__ __forceinline__ void mfma_word(const uint64_t (&xa)[RA], const uint64_t (&xb)[RB],
                                           typename Acc<FMT>::type (&acc)[RA][RB]) {
   if constexpr (FMT == FMT_F4) {
@@ -83,23 +84,54 @@ __device__ __forceinline__ void mfma_word(const uint64_t (&xa)[RA], const uint64
               oa[f], ob[g], acc[f][g], 4, 4, 0, 127, 0, 127);
     }
     return;
+  } else if constexpr (!WIDE) {
+#pragma unroll
+    for (int hw = 0; hw < 2; ++hw) {
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        v4i oa[RA], ob[RB];
+#pragma unroll
+        for (int f = 0; f < RA; ++f) oa[f] = expand4<SEMI>((uint32_t)(xa[f] >> (32 * hw)), 4 * s);
+#pragma unroll
+        for (int g = 0; g < RB; ++g) ob[g] = expand4<SEMI>((uint32_t)(xb[g] >> (32 * hw)), 4 * s);
+#pragma unroll
+        for (int f = 0; f < RA; ++f)
+#pragma unroll
+          for (int g = 0; g < RB; ++g)
+            acc[f][g] = __builtin_amdgcn_mfma_i32_32x32x32_i8(oa[f], ob[g], acc[f][g], 0, 0, 0);
+      }
+    }
   } else {
 #pragma unroll
-  for (int hw = 0; hw < 2; ++hw) {
-#pragma unroll
     for (int s = 0; s < 2; ++s) {
-      v4i oa[RA], ob[RB];
+      // The rows of the longer side expand both 32-bit halves of a word at once: one
+      // 64-bit shift and two masks give dword d of each half, where the 32-bit form takes
+      // two shifts and two masks.  Holding both halves for every row would need more
+      // registers than two waves per SIMD leave, so the other side stays 32-bit.
+      constexpr bool BW = RB >= RA;
+      v4i ow[2][BW ? RB : RA];
 #pragma unroll
-      for (int f = 0; f < RA; ++f) oa[f] = expand4<SEMI>((uint32_t)(xa[f] >> (32 * hw)), 4 * s);
+      for (int g = 0; g < (BW ? RB : RA); ++g)
 #pragma unroll
-      for (int g = 0; g < RB; ++g) ob[g] = expand4<SEMI>((uint32_t)(xb[g] >> (32 * hw)), 4 * s);
+        for (int d = 0; d < 4; ++d) {
+          const uint64_t y = ((BW ? xb[g] : xa[g]) >> (4 * s + d)) & 0x0101010101010101ull;
+          ow[0][g][d] = (int)(uint32_t)y;
+          ow[1][g][d] = (int)(uint32_t)(y >> 32);
+        }
 #pragma unroll
-      for (int f = 0; f < RA; ++f)
+      for (int hw = 0; hw < 2; ++hw) {
+        v4i on[BW ? RA : RB];
 #pragma unroll
-        for (int g = 0; g < RB; ++g)
-          acc[f][g] = __builtin_amdgcn_mfma_i32_32x32x32_i8(oa[f], ob[g], acc[f][g], 0, 0, 0);
+        for (int f = 0; f < (BW ? RA : RB); ++f)
+          on[f] = expand4<SEMI>((uint32_t)((BW ? xa[f] : xb[f]) >> (32 * hw)), 4 * s);
+#pragma unroll
+        for (int f = 0; f < RA; ++f)
+#pragma unroll
+          for (int g = 0; g < RB; ++g)
+            acc[f][g] = __builtin_amdgcn_mfma_i32_32x32x32_i8(BW ? on[f] : ow[hw][f],
+                                                              BW ? ow[hw][g] : on[g], acc[f][g], 0, 0, 0);
+      }
     }
-  }
   }
 }
 
@@ -159,7 +191,7 @@ __device__ __forceinline__ void epilogue(const typename Acc<FMT>::type (&acc)[RA
 // (k = 128 * KV * STEPS bits); the loop then unrolls completely, so the
 // compiler knows every load in flight, and NB register buffers keep the words
 // of step st + NB - 1 in flight while step st computes.
-template <int SEMI, int RA, int RB, int KV, int FMT, int NB = 2, int STEPS = 0>
+template <int SEMI, int RA, int RB, int KV, int FMT, int NB = 2, int STEPS = 0, bool WIDE = true>
 __device__ __forceinline__ void tile(const uint64_t* __restrict__ A, int64_t lda,
                                      const uint64_t* __restrict__ BT, int64_t ldbt,
                                      uint64_t* __restrict__ Cm, int64_t ldc, int64_t m,
@@ -224,7 +256,7 @@ __device__ __forceinline__ void tile(const uint64_t* __restrict__ A, int64_t lda
   };
   auto compute = [&](const uint64_t (&xa)[KV][RA], const uint64_t (&xb)[KV][RB]) {
 #pragma unroll
-    for (int v = 0; v < KV; ++v) mfma_word<SEMI, RA, RB, FMT>(xa[v], xb[v], acc);
+    for (int v = 0; v < KV; ++v) mfma_word<SEMI, RA, RB, FMT, WIDE>(xa[v], xb[v], acc);
   };
   if constexpr (STEPS > 0) {
     static_assert(STEPS >= NB, "an unrolled pipeline needs at least NB steps");
@@ -299,7 +331,7 @@ tail:
         for (int f = 0; f < RA; ++f) xa[f] = wi < kw ? arow[f][w + v] : 0ull;
 #pragma unroll
         for (int g = 0; g < RB; ++g) xb[g] = wi < kw ? brow[g][w + v] : 0ull;
-        mfma_word<SEMI, RA, RB, FMT>(xa, xb, acc);
+        mfma_word<SEMI, RA, RB, FMT, WIDE>(xa, xb, acc);
       }
     }
   }
