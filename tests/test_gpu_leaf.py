@@ -66,7 +66,10 @@ def test_config1_2048_full(bmm, sname, sr, lname, leaf, tile):
 
 RAGGED = [(1, 1, 1), (1, 64, 1), (3, 65, 2), (33, 70, 65), (100, 300, 129), (257, 1000, 200),
           (128, 4096, 64), (130, 129, 33), (64, 8192, 96), (300, 64, 300), (192, 6080, 160),
-          (70, 3840, 130)]
+          (70, 3840, 130),
+          # k = 2048 with unpadded pitches (entries 12 and 15): the recursion's leaf length,
+          # with an odd number of 64-column wave tiles
+          (130, 2048, 130), (64, 4096, 200), (200, 2048, 70), (250, 2048, 260)]
 
 
 @pytest.mark.parametrize("sname,sr", SEMIRINGS)
