@@ -229,3 +229,54 @@ def test_batched_4096_sampled(bmm):
             Ah = bmmgen.fill_cpu(m, k, seed, bmmgen.batched_tag(p, "A"), dist)
             X = bmmgen.freivalds_vectors(m, 2, seed + p)
             assert all(oracle.freivalds(Ah, Bh, got, m, k, n, X)), (p, m, k, n)
+
+
+@pytest.mark.timeout(900)
+def test_ooc_n262144_sampled_rows_freivalds(bmm):
+    """The out-of-core products as the benchmark runs them: n = 2^18 with A, B and C
+    in page-locked host memory (24 GiB) and blocks of 2^17 bits; GF(2) with one host
+    level of the recursion and in the cubic block order (Bernoulli(1/2) bits), Boolean
+    in the block order (Bernoulli(2^-9) bits), int8 leaves.  256 stratified rows of
+    each product against the oracle, and 4 Freivalds vectors on each GF(2) product."""
+    import torch
+    n, blk = 1 << 18, 1 << 17
+    nw = n // 64
+    seed = bmmgen.config_seed(4)
+    announce("full ooc n=2^18: pinned buffers")
+    A = torch.empty((n, nw), dtype=torch.int64, pin_memory=True)
+    B = torch.empty((n, nw), dtype=torch.int64, pin_memory=True)
+    C = torch.empty((n, nw), dtype=torch.int64, pin_memory=True)
+    slab = torch.empty((1 << 15, nw), dtype=torch.int64, device="cuda")
+    rows = bmmgen.stratified_rows(n, 256, seed)
+    runs = [("gf2_host_levels", oracle.GF2, bmmgen.Dist.half(), 0),
+            ("gf2_block_order", oracle.GF2, bmmgen.Dist.half(), bmm.FLAG_OOC_BLOCK_ORDER),
+            ("boolean_block_order", oracle.BOOLEAN, bmmgen.Dist.pow2(9), 0)]
+    made, want, X, lhs = None, None, None, None
+    for name, sr, dist, flags in runs:
+        if made != (dist.kind, dist.param):
+            announce("full ooc n=2^18: operands and oracle", name)
+            for dst, tag in [(A, bmmgen.TAG_A), (B, bmmgen.TAG_B)]:
+                for r0 in range(0, n, slab.shape[0]):
+                    bmmgen.fill_tensor(slab, slab.shape[0], n, seed, tag, dist, row0=r0)
+                    dst[r0:r0 + slab.shape[0]].copy_(slab)
+            torch.cuda.synchronize()
+            Bh = bmmgen.fill_cpu(n, n, seed, bmmgen.TAG_B, dist)
+            Ar = bmmgen.fill_rows_cpu(rows, n, seed, bmmgen.TAG_A, dist)
+            want = oracle.rows(Ar, Bh, n, n, sr)
+            if sr == oracle.GF2:
+                X = bmmgen.freivalds_vectors(n, 4, seed)
+                Ah = bmmgen.fill_cpu(n, n, seed, bmmgen.TAG_A, dist)
+                lhs = [oracle.vecmat(oracle.vecmat(x, Ah, n, n), Bh, n, n) for x in X]
+                del Ah
+            del Bh
+            made = (dist.kind, dist.param)
+        announce("full ooc n=2^18", name)
+        C.fill_(-1)
+        bmm.bmm_ooc(sr, A, B, C, n, n, n, block=blk,
+                    options=bmm.Options(leaf=bmm.LEAF_MFMA_I8, flags=flags))
+        Ch = C.numpy().view(np.uint64)
+        assert np.array_equal(Ch[rows], want), name
+        if sr == oracle.GF2:
+            ok = [np.array_equal(lhs[i], oracle.vecmat(x, Ch, n, n)) for i, x in enumerate(X)]
+            assert all(ok), (name, ok)
+    del A, B, C, slab
