@@ -121,6 +121,8 @@ int build_plan(const bmm_problem* problems, int64_t count, const bmm_options* op
     // the problem's items, in banded order, split into contiguous ranges over the
     // queues; the odd items left over rotate from problem to problem
     const uint64_t items = (uint64_t)items_m * (uint64_t)items_n;
+    if (items >= ((uint64_t)1 << 32))  // segments hold a problem's item index in 32 bits
+      return bfail(BMM_E_UNSUPPORTED, "problem %ld: too many work items", (long)i);
     const uint64_t base = items / kXcds, rem = items % kXcds;
     uint64_t lo = 0;
     for (int xi = 0; xi < kXcds; ++xi) {
