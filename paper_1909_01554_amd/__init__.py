@@ -155,6 +155,62 @@ def _ld(t):
     return t.stride(0)
 
 
+def _is_tensor(t):
+    try:
+        import torch
+    except ImportError:
+        return False
+    return isinstance(t, torch.Tensor)
+
+
+def _span(t):
+    """64-bit words addressable from t.data_ptr() to the end of its storage."""
+    return t.untyped_storage().nbytes() // 8 - t.storage_offset()
+
+
+def _mat(t, name, rows, cols_bits, device=True):
+    """Check a packed matrix operand before its pointer crosses the C ABI: an
+    8-byte integer tensor, 2-D with contiguous rows, at least rows x
+    words(cols_bits) words, on a GPU (device=False: page-locked host memory).
+    The library sees only a pointer and a pitch, so a tensor smaller than the
+    sizes claim would otherwise be read or written out of bounds."""
+    if not _is_tensor(t):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.element_size() != 8 or t.is_floating_point() or t.is_complex():
+        raise ValueError(f"{name} must hold 64-bit words (torch.int64 or torch.uint64), "
+                         f"not {t.dtype}")
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError(f"{name} must be 2-D with contiguous rows")
+    if rows > 0 and cols_bits > 0:
+        if t.shape[0] < rows or t.shape[1] < words(cols_bits):
+            raise ValueError(f"{name} has shape {tuple(t.shape)}; the sizes need at least "
+                             f"{rows} x {words(cols_bits)} words")
+    if device is True and not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if device is False and t.is_cuda:
+        raise ValueError(f"{name} must be in (page-locked) host memory")
+    return t
+
+
+def _sizes(m, k, n):
+    for v, nm in ((m, "m"), (k, "k"), (n, "n")):
+        if int(v) < 0:
+            raise ValueError(f"{nm} = {v} is negative")
+
+
+def _operands(A, B, C, m, k, n, b_transposed, device=True):
+    """Shapes and types of all three operands first, then where they live."""
+    _sizes(m, k, n)
+    mats = [(C, "C", m, n)]
+    if m > 0 and n > 0 and k > 0:
+        mats = [(A, "A", m, k), (B, "B (transposed)", n, k) if b_transposed else
+                (B, "B", k, n)] + mats
+    for t, name, r, c in mats:
+        _mat(t, name, r, c, device=None)
+    for t, name, r, c in mats:
+        _mat(t, name, r, c, device=device)
+
+
 def _opts(options, flags):
     o = Options()
     if options is not None:
@@ -166,6 +222,8 @@ def _opts(options, flags):
 
 def _product(fn, A, B, C, m, k, n, options, flags, stream):
     o = _opts(options, flags)
+    _operands(A, B, C, m, k, n, bool(o.flags & FLAG_B_TRANSPOSED),
+              device=not (o.flags & FLAG_HOST_OPERANDS))
     _check(fn(_ptr(A), _ld(A), _ptr(B), _ld(B), _ptr(C), _ld(C), m, k, n, ctypes.byref(o),
               _stream(C, stream)))
     return C
@@ -201,6 +259,9 @@ def bmm_gf2_strassen(A, B, C, m, k, n, workspace, depth=-1, options=None, b_tran
     o = _opts(options, (FLAG_B_TRANSPOSED if b_transposed else 0)
               | (FLAG_ALT_BASIS_IO if alt_basis_io else 0)
               | (FLAG_ACCUMULATE if accumulate else 0))
+    _operands(A, B, C, m, k, n, b_transposed)
+    if not _is_tensor(workspace) or not workspace.is_cuda or not workspace.is_contiguous():
+        raise ValueError("the workspace must be a contiguous GPU tensor")
     nbytes = workspace.numel() * workspace.element_size()
     _check(_c_strassen(_ptr(A), _ld(A), _ptr(B), _ld(B), _ptr(C), _ld(C), m, k, n, depth,
                        _ptr(workspace), nbytes, ctypes.byref(o), _stream(C, stream)))
@@ -210,6 +271,11 @@ def bmm_gf2_strassen(A, B, C, m, k, n, workspace, depth=-1, options=None, b_tran
 def _problems(problems):
     arr = (Problem * len(problems))()
     for i, p in enumerate(problems):
+        try:
+            _operands(p["A"], p["B"], p["C"], p["m"], p["k"], p["n"],
+                      bool(p.get("b_transposed")))
+        except (TypeError, ValueError) as e:
+            raise type(e)(f"problem {i}: {e}") from None
         arr[i] = Problem(p["semiring"], p["m"], p["k"], p["n"], p["A"].data_ptr(),
                          p["B"].data_ptr(), p["C"].data_ptr(), _ld(p["A"]), _ld(p["B"]),
                          _ld(p["C"]), 1 if p.get("b_transposed") else 0)
@@ -271,6 +337,11 @@ def bmm_autotune_batched(problems):
 
 
 def bmm_transpose(src, dst, rows, cols, stream=None):
+    _sizes(rows, cols, 0)
+    if rows > 0 and cols > 0:
+        for dev in (None, True):
+            _mat(src, "src", rows, cols, device=dev)
+            _mat(dst, "dst", cols, rows, device=dev)
     _check(_c_transpose(_ptr(src), _ld(src), _ptr(dst), _ld(dst), rows, cols,
                         _stream(dst, stream)))
     return dst
@@ -278,13 +349,37 @@ def bmm_transpose(src, dst, rows, cols, stream=None):
 
 def bmm_basis_change(X, rows, row_words, depth, inverse=False, scheme=SCHEME_SELF_INVERSE,
                      transposed=False, stream=None):
+    _sizes(rows, row_words, 0)
+    if depth > 0:
+        _mat(X, "X", rows, 64 * row_words)
     _check(_c_basis(_ptr(X), _ld(X), rows, row_words, depth, 1 if inverse else 0, scheme,
                     1 if transposed else 0, _stream(X, stream)))
     return X
 
 
+def _extent(t, name, parents, stride, rows, ld, row_words, device=None):
+    """The C call addresses words [0, (parents-1)*stride + (rows-1)*ld + row_words) from
+    t.data_ptr(): t's storage must hold them (and t must be an 8-byte GPU tensor)."""
+    if not _is_tensor(t) or t.element_size() != 8 or t.is_floating_point():
+        raise ValueError(f"{name} must be a tensor of 64-bit words")
+    if device and not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if parents > 0 and rows > 0 and row_words > 0:
+        need = (parents - 1) * stride + (rows - 1) * ld + row_words
+        if stride < 0 or ld < row_words or need > _span(t):
+            raise ValueError(f"{name} holds {_span(t)} words from its start; the sizes "
+                             f"address {need}")
+
+
 def bmm_expand(side, levels, src, ldp, stride_p, dst, rows, words_, parents,
                scheme=SCHEME_SELF_INVERSE, stream=None):
+    _sizes(rows, words_, parents)
+    if rows > 0 and words_ > 0 and parents > 0 and levels in (1, 2):
+        c = 7 ** levels
+        cw = (rows >> levels) * (words_ >> levels)
+        for dev in (None, True):
+            _extent(src, "src", parents, stride_p, rows, ldp, words_, dev)
+            _extent(dst, "dst", 1, 0, 1, cw * c * parents, cw * c * parents, dev)
     _check(_c_expand(side, levels, scheme, _ptr(src), ldp, stride_p, _ptr(dst), rows, words_,
                      parents, _stream(dst, stream)))
     return dst
@@ -292,6 +387,13 @@ def bmm_expand(side, levels, src, ldp, stride_p, dst, rows, words_, parents,
 
 def bmm_compress(levels, src, dst, ldp, stride_p, rows, words_, parents,
                  scheme=SCHEME_SELF_INVERSE, stream=None):
+    _sizes(rows, words_, parents)
+    if rows > 0 and words_ > 0 and parents > 0 and levels in (1, 2):
+        c = 7 ** levels
+        cw = (rows >> levels) * (words_ >> levels)
+        for dev in (None, True):
+            _extent(src, "src", 1, 0, 1, cw * c * parents, cw * c * parents, dev)
+            _extent(dst, "dst", parents, stride_p, rows, ldp, words_, dev)
     _check(_c_compress(levels, scheme, _ptr(src), _ptr(dst), ldp, stride_p, rows, words_,
                        parents, _stream(dst, stream)))
     return dst
@@ -300,14 +402,22 @@ def bmm_compress(levels, src, dst, ldp, stride_p, rows, words_, parents,
 def bmm_ooc(semiring, A, B, C, m, k, n, block=0, options=None):
     """Out-of-core product of page-locked host matrices (numpy or pinned torch
     CPU tensors) streamed through HBM.  Synchronous; returns the seconds spent."""
-    def hptr(t):
-        if hasattr(t, "data_ptr"):
+    def hptr(t, name, rows, cols):
+        if _is_tensor(t):
+            _mat(t, name, rows, cols, device=False)
             return ctypes.c_void_p(t.data_ptr()), t.stride(0)
+        if (getattr(t, "ndim", 0) != 2 or t.itemsize != 8 or t.dtype.kind not in "iu"
+                or t.strides[1] != 8):
+            raise ValueError(f"{name} must be a 2-D array of 64-bit words with contiguous rows")
+        if rows > 0 and cols > 0 and (t.shape[0] < rows or t.shape[1] < words(cols)):
+            raise ValueError(f"{name} has shape {t.shape}; the sizes need at least "
+                             f"{rows} x {words(cols)} words")
         return ctypes.c_void_p(t.ctypes.data), t.strides[0] // 8
+    _sizes(m, k, n)
     o = _opts(options, FLAG_HOST_OPERANDS)
-    a, lda = hptr(A)
-    b, ldb = hptr(B)
-    c, ldc = hptr(C)
+    a, lda = hptr(A, "A", m, k)
+    b, ldb = hptr(B, "B", k, n)
+    c, ldc = hptr(C, "C", m, n)
     secs = ctypes.c_double(0.0)
     _check(_c_ooc(semiring, a, lda, b, ldb, c, ldc, m, k, n, block, ctypes.byref(o),
                   ctypes.byref(secs)))

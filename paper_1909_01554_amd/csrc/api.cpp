@@ -41,6 +41,9 @@ namespace {
 
 int check_hip(hipError_t e, const char* what) {
   if (e == hipSuccess) return BMM_OK;
+  if (e == kGridTooLarge)
+    return fail(BMM_E_UNSUPPORTED, "%s: the launch would need 2^32 or more work-items "
+                "(split the product into smaller blocks)", what);
   return fail(BMM_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 

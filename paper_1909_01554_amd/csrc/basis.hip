@@ -105,6 +105,11 @@ hipError_t launch_pass(uint64_t* X, int64_t ld, int64_t stride, int64_t rows, in
                        int64_t batch, int level0, int inverse, int sch, int transposed,
                        hipStream_t s) {
   if (sch == BMM_SCHEME_CHAINING) {
+    // the chaining programs are not symmetric in the 01 and 10 quadrants, so a transposed
+    // operand takes its own instantiation in both directions
+    if (inverse && transposed)
+      return launch_pass4<R, BMM_SCHEME_CHAINING, 1, 1>(X, ld, stride, rows, row_words, batch,
+                                                        level0, s);
     if (inverse)
       return launch_pass4<R, BMM_SCHEME_CHAINING, 1, 0>(X, ld, stride, rows, row_words, batch,
                                                         level0, s);

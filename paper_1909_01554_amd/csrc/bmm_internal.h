@@ -15,6 +15,14 @@ enum Semiring { GF2 = 0, BOOLEAN = 1 };
 // Record a message for bmm_last_error() (thread-local) and return `code`.
 int set_error(int code, const char* fmt, ...);
 
+// A dispatch covers fewer than 2^32 work-items (the grid size of an AQL packet is
+// 32 bits).  Launchers whose grid would reach that return kGridTooLarge without
+// launching; the entry points report it as BMM_E_UNSUPPORTED.
+constexpr hipError_t kGridTooLarge = hipErrorInvalidConfiguration;
+inline bool grid_fits(int64_t blocks, int64_t threads) {
+  return blocks >= 0 && blocks * threads < ((int64_t)1 << 32) && blocks < ((int64_t)1 << 31);
+}
+
 // A batch of independent leaf products C_b (m x n) = A_b (m x k) * B_b (k x n),
 // with B_b given transposed as BT_b (n x k).  Operand b starts at base + b*stride
 // (strides in words).  accumulate: C ^= AB (GF(2)) or C |= AB (Boolean).

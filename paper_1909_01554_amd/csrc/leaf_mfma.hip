@@ -57,6 +57,7 @@ hipError_t launch_t(const LeafBatch& p, hipStream_t s) {
   const int64_t tiles_n = (((p.n + 63) / 64) * 64 + TN - 1) / TN;
   const int64_t blocks = ((tiles_m + 1) / 2) * ((tiles_n + 1) / 2) * p.batch;
   if (blocks == 0) return hipSuccess;
+  if (!grid_fits(blocks, 256)) return kGridTooLarge;
   const bool aligned16 = ((reinterpret_cast<uintptr_t>(p.A) | reinterpret_cast<uintptr_t>(p.BT)) & 15) == 0 &&
                          ((p.lda | p.ldbt | p.strideA | p.strideB) & 1) == 0;
   const dim3 g((unsigned)blocks), b(256);

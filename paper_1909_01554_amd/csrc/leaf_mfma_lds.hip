@@ -140,6 +140,7 @@ hipError_t launch_sf(const LeafBatch& p, hipStream_t s) {
   const int64_t grid_n = (p.n + L_TN - 1) / L_TN;
   const int64_t blocks = grid_m * grid_n * p.batch;
   if (blocks == 0) return hipSuccess;
+  if (!grid_fits(blocks, LT)) return kGridTooLarge;
   static bool configured = false;
   if (!configured) {
     hipError_t e = hipFuncSetAttribute(

@@ -156,6 +156,7 @@ hipError_t launch_leaf_valu(int semiring, const LeafBatch& p, int /*tile*/, hipS
   const int64_t tiles_m = (p.m + TM - 1) / TM;
   const int64_t tiles_n = (p.n + TN - 1) / TN;
   const int64_t blocks = tiles_m * tiles_n * p.batch;
+  if (!grid_fits(blocks, 256)) return kGridTooLarge;
   if (semiring == GF2)
     hipLaunchKernelGGL(leaf_valu_kernel<GF2>, dim3((unsigned)blocks), dim3(256), 0, s, p,
                        tiles_m, tiles_n);

@@ -62,7 +62,8 @@ __host__ __device__ __forceinline__ void inv(uint64_t& x00, uint64_t& x01, uint6
 template <int SCH, int INV, int T>
 constexpr int written() {
   if (SCH == BMM_SCHEME_SELF_INVERSE) return INV ? 0x6 : 0x8;  // 01+10 / 11
-  if (SCH == BMM_SCHEME_CHAINING) return INV ? 0xC : (T ? 0xA : 0xC);  // 10+11 (01+11 transposed)
+  // chaining: both directions write 10 and 11 (stored 01 and 11 when transposed)
+  if (SCH == BMM_SCHEME_CHAINING) return T ? 0xA : 0xC;
   return 0;
 }
 

@@ -94,6 +94,7 @@ hipError_t launch_transpose(const uint64_t* src, int64_t lds, int64_t strideS, u
   const int64_t n_rt = (rows + TR_ROWS - 1) / TR_ROWS;
   const int64_t n_wt = ((cols + 63) / 64 + TR_WORDS - 1) / TR_WORDS;
   const int64_t blocks = n_rt * n_wt * batch;
+  if (!grid_fits(blocks, 256)) return kGridTooLarge;
   hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)blocks), dim3(256), 0, s, src, lds,
                      strideS, dst, ldd, strideD, rows, cols, n_rt, n_wt, batch);
   return hipGetLastError();

@@ -37,40 +37,90 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_argument_errors_without_gpu():
+    """The C side rejects bad sizes, pitches and overlaps before any device work
+    (called through ctypes with pointers that are never dereferenced)."""
     import paper_1909_01554_amd as bmm
+    vp = ctypes.c_void_p
+    o = bmm.Options()
 
-    class Fake:
-        """A stand-in with a data pointer and a row stride; never dereferenced."""
-        def __init__(self, ptr, rows, ld):
-            self._p, self._r, self._ld = ptr, rows, ld
+    def gf2(a, lda, b, ldb, c, ldc, m, k, n, fn=None):
+        return (fn or bmm._c_gf2)(vp(a), lda, vp(b), ldb, vp(c), ldc, m, k, n,
+                                  ctypes.byref(o), None)
 
-        def data_ptr(self):
-            return self._p
-
-        def dim(self):
-            return 2
-
-        def stride(self, i):
-            return (self._ld, 1)[i]
-
-    A = Fake(0x10000, 8, 1)
-    B = Fake(0x20000, 64, 1)
-    C = Fake(0x30000, 8, 1)
-    with pytest.raises(bmm.BmmError) as e:
-        bmm.bmm_gf2(A, B, C, 8, 128, 64, stream=0)  # lda 1 < 2 words
-    assert e.value.status == -1
-    with pytest.raises(bmm.BmmError) as e:
-        bmm.bmm_boolean(A, B, C, -3, 64, 64, stream=0)
-    assert e.value.status == -1
-    with pytest.raises(bmm.BmmError) as e:
-        bmm.bmm_gf2(A, B, A, 8, 64, 64, stream=0)  # C overlaps A
-    assert e.value.status == -1
+    assert gf2(0x10000, 1, 0x20000, 1, 0x30000, 1, 8, 128, 64) == -1  # lda 1 < 2 words
+    assert gf2(0x10000, 1, 0x20000, 1, 0x30000, 1, -3, 64, 64, bmm._c_boolean) == -1
+    assert gf2(0x10000, 1, 0x20000, 1, 0x10000, 1, 8, 64, 64) == -1  # C overlaps A
+    assert gf2(0x10004, 1, 0x20000, 1, 0x30000, 1, 8, 64, 64) == -1  # misaligned A
+    assert "aligned" in bmm._c_last_error().decode()
     # Strassen size rules are checked before any device work
     with pytest.raises(bmm.BmmError) as e:
         bmm.bmm_gf2_strassen_workspace(1002, 1024, 1024, 3)
     assert e.value.status == -2
     nbytes, ds, dp = bmm.bmm_gf2_strassen_workspace(4096, 4096, 4096, 4)
     assert nbytes > 0 and ds + dp == 4
+
+
+def test_python_binding_checks_tensors():
+    """The binding checks dtype, layout and shape against m, k, n (and the device)
+    before a pointer crosses the ABI, so a caller's mistake is a ValueError and not an
+    out-of-bounds access on the GPU."""
+    import torch
+
+    import paper_1909_01554_amd as bmm
+    m, k, n = 8, 128, 64
+    A = torch.zeros((m, 2), dtype=torch.int64)
+    B = torch.zeros((k, 1), dtype=torch.int64)
+    C = torch.zeros((m, 1), dtype=torch.int64)
+    bad = [
+        (A.to(torch.int32), B, C, "A"),                        # 4-byte words
+        (A, B.to(torch.float64), C, "B"),                      # floating point
+        (A[:, :1], B, C, "A"),                                 # k needs 2 words per row
+        (A, B[:64], C, "B"),                                   # B needs k rows
+        (A, B, C[:4], "C"),                                    # C needs m rows
+        (A.t(), B, C, "A"),                                    # rows not contiguous
+        (A, B, C, "GPU"),                                      # right shapes, host memory
+    ]
+    for a, b, c, what in bad:
+        with pytest.raises(ValueError, match=what):
+            bmm.bmm_gf2(a, b, c, m, k, n)
+        with pytest.raises(ValueError, match=what):
+            bmm.bmm_boolean(a, b, c, m, k, n)
+    with pytest.raises(ValueError, match="negative"):
+        bmm.bmm_gf2(A, B, C, -1, k, n)
+    with pytest.raises(TypeError):
+        bmm.bmm_gf2(A.numpy(), B, C, m, k, n)
+    # B passed transposed must be n x k
+    with pytest.raises(ValueError, match="transposed"):
+        bmm.bmm_gf2(A, torch.zeros((n - 1, 2), dtype=torch.int64), C, m, k, n,
+                    b_transposed=True)
+    # Strassen: operands as above, and the workspace must be a GPU tensor
+    with pytest.raises(ValueError, match="A"):
+        bmm.bmm_gf2_strassen(A[:, :1], B, C, m, k, n, torch.zeros(8, dtype=torch.int64))
+    with pytest.raises(ValueError, match="GPU"):
+        bmm.bmm_gf2_strassen(A, B, C, m, k, n, torch.zeros(8, dtype=torch.int64))
+    # batched problems name the problem
+    prob = dict(semiring=bmm.GF2, m=m, k=k, n=n, A=A, B=B[:10], C=C)
+    with pytest.raises(ValueError, match="problem 0"):
+        bmm.bmm_batched([prob])
+    with pytest.raises(ValueError, match="problem 0"):
+        bmm.BatchedPlan([prob])
+    # stage entry points
+    with pytest.raises(ValueError, match="dst"):
+        bmm.bmm_transpose(torch.zeros((64, 1), dtype=torch.int64),
+                          torch.zeros((63, 1), dtype=torch.int64), 64, 64)
+    with pytest.raises(ValueError, match="X"):
+        bmm.bmm_basis_change(torch.zeros((64, 1), dtype=torch.int64), 64, 2, 1)
+    with pytest.raises(ValueError, match="src"):
+        bmm.bmm_expand(0, 1, torch.zeros(10, dtype=torch.int64), 2, 0,
+                       torch.zeros(100, dtype=torch.int64), 4, 2, 1)
+    with pytest.raises(ValueError, match="dst"):
+        bmm.bmm_compress(1, torch.zeros(100, dtype=torch.int64),
+                         torch.zeros(5, dtype=torch.int64), 2, 0, 4, 2, 1)
+    # out of core: host operands of the right shapes
+    import numpy as np
+    with pytest.raises(ValueError, match="B"):
+        bmm.bmm_ooc(bmm.GF2, np.zeros((m, 2), np.uint64), np.zeros((k - 1, 1), np.uint64),
+                    np.zeros((m, 1), np.uint64), m, k, n)
 
 
 def test_workspace_formula():
@@ -132,3 +182,20 @@ def test_leaf_choice_follows_the_table(tmp_path):
     assert bmm.bmm_leaf_choice(bmm.GF2, 256, 256, 256) == (2, 2)
     with pytest.raises(bmm.BmmError):
         bmm.bmm_leaf_choice(7, 1, 1, 1)
+
+
+def test_launch_grid_bound():
+    """A launch whose grid would reach 2^32 work-items is refused on the host with
+    BMM_E_UNSUPPORTED (never launched truncated): m = n = 2^19 with the VALU leaf
+    (128 x 128 per 256-thread workgroup) and the int8 64 x 64 tile (128 x 128 per
+    workgroup) both need 2^24 workgroups.  Pointers are never dereferenced."""
+    import paper_1909_01554_amd as bmm
+    vp = ctypes.c_void_p
+    m = n = 1 << 19
+    k = 64
+    A, B, C = 1 << 32, 2 << 32, 16 << 32
+    for leaf, tile in [(bmm.LEAF_VALU, 1), (bmm.LEAF_MFMA_I8, 2)]:
+        o = bmm.Options(leaf=leaf, tile=tile, flags=bmm.FLAG_B_TRANSPOSED)
+        rc = bmm._c_gf2(vp(A), 1, vp(B), 1, vp(C), n // 64, m, k, n, ctypes.byref(o), None)
+        assert rc == -2, (leaf, tile, rc)
+        assert "2^32" in bmm._c_last_error().decode()

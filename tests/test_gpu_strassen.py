@@ -54,19 +54,24 @@ def test_basis_change(bmm, depth, inverse, scheme):
 
 
 @pytest.mark.parametrize("depth", [1, 3, 6])
+@pytest.mark.parametrize("inverse", [0, 1])
 @pytest.mark.parametrize("scheme", [0, 1])
-def test_basis_change_transposed(bmm, depth, scheme):
-    """On a right operand stored transposed, the forward change equals the
-    transpose of the change applied to the operand itself."""
+def test_basis_change_transposed(bmm, depth, inverse, scheme):
+    """On a matrix stored transposed, the forward (and the inverse) change equals the
+    transpose of the change applied to the matrix itself.  The chaining programs are
+    not symmetric in the 01 and 10 quadrants, so this checks the transposed
+    instantiation of each direction."""
     from oracle import brute
     rows, nw = 3 << depth, 2 << depth
     cols = 64 * nw
-    Xs = rand_words(rows, nw, 70 + depth)  # stored: B^T, rows x cols bits
+    Xs = rand_words(rows, nw, 70 + depth + 10 * inverse)  # stored: X^T, rows x cols bits
     Xd = to_dev(Xs)
-    announce("basis transposed", depth, scheme)
-    bmm.bmm_basis_change(Xd, rows, nw, depth, scheme=scheme, transposed=True)
+    announce("basis transposed", depth, inverse, scheme)
+    bmm.bmm_basis_change(Xd, rows, nw, depth, inverse=bool(inverse), scheme=scheme,
+                         transposed=True)
     B = brute.unpack(Xs, cols).T.copy()  # cols x rows bits
-    want = brute.pack(strassen.basis(B, depth, DECS[scheme].fwd).T.copy())
+    prog = DECS[scheme].inv if inverse else DECS[scheme].fwd
+    want = brute.pack(strassen.basis(B, depth, prog).T.copy())
     assert np.array_equal(from_dev(Xd), want)
 
 
