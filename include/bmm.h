@@ -268,6 +268,24 @@ int bmm_autotune_strassen(const uint64_t* A, int64_t lda, const uint64_t* B, int
 int bmm_autotune_save(const char* path);
 int bmm_autotune_load(const char* path);
 
+/* VALU roofline calibration (the bit-operation peak of section 1.2 is a device's
+ * lane-operation rate times its word width; this measures that rate for the
+ * three-input v_bitop3_b32 that the VALU leaf folds with, instead of assuming
+ * it).  waves_per_simd (1..8) waves on every SIMD of every CU each fold 16
+ * independent 32-bit chains, one v_bitop3_b32 per chain per round, for `rounds`
+ * rounds (a positive multiple of 4), with no memory traffic in the timed loop;
+ * every wave reads the core-clock counter (s_memtime) and the constant-rate
+ * counter before and after.  Outputs (any may be NULL):
+ *   lane_ops_per_clk_cu: waves_per_simd x 64 lanes x 4 SIMDs x the median over
+ *                        waves of instructions per core cycle;
+ *   clock_ghz:           median core clock of the waves;
+ *   seconds:             the timed launch by HIP events;
+ *   aggregate_bops:      2 x 32 bit operations per lane operation, all waves,
+ *                        over `seconds`.
+ * Synchronous on the default stream; allocates a few MiB. */
+int bmm_calibrate_valu(int waves_per_simd, int64_t rounds, double* lane_ops_per_clk_cu,
+                       double* clock_ghz, double* seconds, double* aggregate_bops);
+
 const char* bmm_status_string(int status);
 const char* bmm_last_error(void);
 const char* bmm_version(void);

@@ -25,7 +25,7 @@ __all__ = [
     "bmm_compress", "bmm_ooc", "bmm_autotune_cubic", "bmm_autotune_leaf",
     "bmm_autotune_strassen", "bmm_autotune_set", "bmm_autotune_batched", "bmm_autotune_save",
     "bmm_autotune_load", "bmm_leaf_tiles", "bmm_leaf_tile_shape", "bmm_leaf_choice", "bmm_version",
-    "bmm_finalize", "library_path",
+    "bmm_finalize", "library_path", "bmm_calibrate_valu",
 ]
 
 GF2, BOOLEAN = 0, 1
@@ -124,6 +124,7 @@ _c_tune_load = _sig("bmm_autotune_load", [ctypes.c_char_p])
 _c_tiles = _sig("bmm_leaf_tiles", [_int, ctypes.POINTER(_int)])
 _c_tile_shape = _sig("bmm_leaf_tile_shape", [_int, _int, ctypes.POINTER(_int),
                                              ctypes.POINTER(_int)])
+_c_calib = _sig("bmm_calibrate_valu", [_int, _i64] + [ctypes.POINTER(ctypes.c_double)] * 4)
 _c_last_error = _sig("bmm_last_error", [], ctypes.c_char_p)
 _c_version = _sig("bmm_version", [], ctypes.c_char_p)
 _c_finalize = _sig("bmm_finalize", [], None)
@@ -490,6 +491,15 @@ def bmm_leaf_tile_shape(leaf, tile):
     c = _int(0)
     _check(_c_tile_shape(leaf, tile, ctypes.byref(r), ctypes.byref(c)))
     return r.value, c.value
+
+
+def bmm_calibrate_valu(waves_per_simd=2, rounds=1 << 20):
+    """Measured v_bitop3_b32 issue rate (bmm_calibrate_valu): dict with
+    lane_ops_per_clk_cu, clock_ghz, seconds and aggregate_bops."""
+    out = [ctypes.c_double(0.0) for _ in range(4)]
+    _check(_c_calib(waves_per_simd, rounds, *[ctypes.byref(v) for v in out]))
+    return dict(zip(("lane_ops_per_clk_cu", "clock_ghz", "seconds", "aggregate_bops"),
+                    (v.value for v in out)))
 
 
 def bmm_version():

@@ -204,18 +204,30 @@ int validate_product(const uint64_t* A, int64_t lda, const uint64_t* B, int64_t 
   return BMM_OK;
 }
 
-int cubic(int semiring, const uint64_t* A, int64_t lda, const uint64_t* B, int64_t ldb,
-          uint64_t* C, int64_t ldc, int64_t m, int64_t k, int64_t n, const bmm_options* opt,
-          void* stream) {
+}  // namespace
+
+namespace bmm {
+
+int cubic_product(int semiring, const uint64_t* A, int64_t lda, const uint64_t* B, int64_t ldb,
+                  uint64_t* C, int64_t ldc, int64_t m, int64_t k, int64_t n,
+                  const bmm_options* opt, void* stream, const BtScratch* caller_bt) {
   const bmm_options o = opt ? *opt : defaults();
-  if (o.flags & BMM_FLAG_HOST_OPERANDS)
-    return fail(BMM_E_UNSUPPORTED, "host operands: use the out-of-core entry (bmm_ooc)");
   const bool b_t = (o.flags & BMM_FLAG_B_TRANSPOSED) != 0;
   BMM_TRY(validate_product(A, lda, B, ldb, C, ldc, m, k, n, b_t));
   if (m == 0 || n == 0) return BMM_OK;
-  hipStream_t s = (hipStream_t)stream;
   const bool acc = (o.flags & BMM_FLAG_ACCUMULATE) != 0;
   const int64_t kw = words_of(k);
+  const size_t bt_bytes = (size_t)n * kw * 8;
+  if (caller_bt && k > 0 && !b_t && bt_bytes > caller_bt->bytes)
+    return fail(BMM_E_UNSUPPORTED,
+                "B^T needs %zu bytes of scratch and this entry point has %zu: pass B "
+                "transposed (BMM_FLAG_B_TRANSPOSED) or call bmm_gf2 / bmm_boolean",
+                bt_bytes, caller_bt->bytes);
+  void* buf = nullptr;
+  if (caller_bt && k > 0 && !b_t) {
+    BMM_TRY(caller_bt->get(&buf));
+  }
+  hipStream_t s = (hipStream_t)stream;
   if (k == 0) {
     if (!acc) HIP_TRY(launch_zero(C, ldc, m, words_of(n), s), "zero");
     return BMM_OK;
@@ -223,8 +235,7 @@ int cubic(int semiring, const uint64_t* A, int64_t lda, const uint64_t* B, int64
   const uint64_t* BT = B;
   int64_t ldbt = ldb;
   if (!b_t) {
-    void* buf = nullptr;
-    BMM_TRY(scratch((size_t)n * kw * 8, &buf));
+    if (!buf) BMM_TRY(scratch(bt_bytes, &buf));
     HIP_TRY(launch_transpose(B, ldb, 0, (uint64_t*)buf, kw, 0, k, n, 1, s), "transpose");
     BT = (const uint64_t*)buf;
     ldbt = kw;
@@ -233,6 +244,19 @@ int cubic(int semiring, const uint64_t* A, int64_t lda, const uint64_t* B, int64
   pick_leaf(semiring, m, k, n, 1, o, &leaf, &tile);
   LeafBatch p{A, lda, 0, BT, ldbt, 0, C, ldc, 0, m, k, n, 1, acc ? 1 : 0};
   return run_leaf(semiring, leaf, tile, p, s);
+}
+
+}  // namespace bmm
+
+namespace {
+
+int cubic(int semiring, const uint64_t* A, int64_t lda, const uint64_t* B, int64_t ldb,
+          uint64_t* C, int64_t ldc, int64_t m, int64_t k, int64_t n, const bmm_options* opt,
+          void* stream) {
+  const bmm_options o = opt ? *opt : defaults();
+  if (o.flags & BMM_FLAG_HOST_OPERANDS)
+    return fail(BMM_E_UNSUPPORTED, "host operands: use the out-of-core entry (bmm_ooc)");
+  return cubic_product(semiring, A, lda, B, ldb, C, ldc, m, k, n, opt, stream, nullptr);
 }
 
 // ---- Strassen plan ----

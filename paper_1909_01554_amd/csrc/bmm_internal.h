@@ -138,6 +138,13 @@ hipError_t launch_random(uint64_t* dst, int64_t words, uint64_t seed, hipStream_
 // Zero a rows x words matrix (a fill kernel, safe under graph capture).
 hipError_t launch_zero(uint64_t* dst, int64_t ld, int64_t rows, int64_t words, hipStream_t s);
 
+// VALU issue-rate calibration (calib.hip): `blocks` 256-thread workgroups fold
+// calib_chains() independent chains with one v_bitop3_b32 each per round; every wave
+// stores (core clock start, end, constant clock start, end) at stamps[4 * wave].
+int calib_chains();
+hipError_t launch_valu_rate(uint32_t seed, int64_t rounds, int blocks, uint32_t* sink,
+                            long long* stamps, hipStream_t s);
+
 // Persistent batched leaf over a device-resident problem table.  A work item is
 // one workgroup's 2 x 2 wave tiles of one problem; a problem's items, in banded
 // order, are split into contiguous ranges over kXcds queues (one per XCD), and
@@ -189,6 +196,17 @@ namespace bmm {
 // default rule), as every entry point chooses them.
 void choose_leaf(int semiring, int64_t m, int64_t k, int64_t n, int64_t batch,
                  const bmm_options& o, int* leaf, int* tile);
+// The cubic product behind bmm_gf2 / bmm_boolean.  B^T goes to the library's cached
+// scratch, or, when caller_bt is given, to that fixed buffer (get() returns its
+// device address, set up on first use): requests whose B^T does not fit are
+// refused with BMM_E_UNSUPPORTED before any device work.
+struct BtScratch {
+  size_t bytes;
+  int (*get)(void** out);
+};
+int cubic_product(int semiring, const uint64_t* A, int64_t lda, const uint64_t* B, int64_t ldb,
+                  uint64_t* C, int64_t ldc, int64_t m, int64_t k, int64_t n,
+                  const bmm_options* opt, void* stream, const BtScratch* caller_bt);
 hipError_t to_alt_basis(uint64_t* C, int64_t ldc, int64_t rows, int64_t words, int depth,
                         int scheme, hipStream_t s);
 
