@@ -286,6 +286,25 @@ int bmm_autotune_load(const char* path);
 int bmm_calibrate_valu(int waves_per_simd, int64_t rounds, double* lane_ops_per_clk_cu,
                        double* clock_ghz, double* seconds, double* aggregate_bops);
 
+/* Cubic product that allocates nothing, for callers that cannot call hipMalloc
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation).  Same operation, arguments and errors as bmm_gf2 (semiring =
+ * BMM_GF2) and bmm_boolean (BMM_BOOLEAN), and the same kernels; when B is not
+ * passed transposed, B^T is staged in a fixed device array of
+ * BMM_NOALLOC_SCRATCH_BYTES instead of the library's growable buffer, so
+ * n * ceil(k / 64) * 8 must not exceed that size (else BMM_E_UNSUPPORTED; pass
+ * BMM_FLAG_B_TRANSPOSED to use no scratch at all).  Each device holds its own
+ * copy of the array from the first call on it until the process ends; that
+ * first call looks up its address (hipGetSymbolAddress), later ones touch no
+ * runtime state.  All calls on one device share the array: two such calls that
+ * may overlap on one device (different streams, or a graph replayed on one
+ * stream while another call runs on a second) race on it and must be ordered
+ * by the caller.  BMM_FLAG_HOST_OPERANDS is refused (BMM_E_UNSUPPORTED). */
+#define BMM_NOALLOC_SCRATCH_BYTES (32u << 20)
+int bmm_cubic_noalloc(int semiring, const uint64_t* A, int64_t lda, const uint64_t* B,
+                      int64_t ldb, uint64_t* C, int64_t ldc, int64_t m, int64_t k, int64_t n,
+                      const bmm_options* opt, void* hip_stream);
+
 const char* bmm_status_string(int status);
 const char* bmm_last_error(void);
 const char* bmm_version(void);

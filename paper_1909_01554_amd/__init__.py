@@ -25,7 +25,7 @@ __all__ = [
     "bmm_compress", "bmm_ooc", "bmm_autotune_cubic", "bmm_autotune_leaf",
     "bmm_autotune_strassen", "bmm_autotune_set", "bmm_autotune_batched", "bmm_autotune_save",
     "bmm_autotune_load", "bmm_leaf_tiles", "bmm_leaf_tile_shape", "bmm_leaf_choice", "bmm_version",
-    "bmm_finalize", "library_path", "bmm_calibrate_valu",
+    "bmm_finalize", "library_path", "bmm_calibrate_valu", "bmm_cubic_noalloc",
 ]
 
 GF2, BOOLEAN = 0, 1
@@ -88,6 +88,8 @@ def _sig(name, args, res=_int):
 _prod_args = [_vp, _i64, _vp, _i64, _vp, _i64, _i64, _i64, _i64, ctypes.POINTER(Options), _vp]
 _c_gf2 = _sig("bmm_gf2", _prod_args)
 _c_boolean = _sig("bmm_boolean", _prod_args)
+_c_noalloc = _sig("bmm_cubic_noalloc", [_int] + _prod_args)
+NOALLOC_SCRATCH_BYTES = 32 << 20  # BMM_NOALLOC_SCRATCH_BYTES
 _c_strassen = _sig("bmm_gf2_strassen", [_vp, _i64, _vp, _i64, _vp, _i64, _i64, _i64, _i64, _int,
                                         _vp, ctypes.c_size_t, ctypes.POINTER(Options), _vp])
 _c_strassen_ws = _sig("bmm_gf2_strassen_workspace",
@@ -241,6 +243,16 @@ def bmm_boolean(A, B, C, m, k, n, options=None, b_transposed=False, accumulate=F
     """C = AB (or C |= AB) over the Boolean algebra by the cubic method."""
     flags = (FLAG_B_TRANSPOSED if b_transposed else 0) | (FLAG_ACCUMULATE if accumulate else 0)
     return _product(_c_boolean, A, B, C, m, k, n, options, flags, stream)
+
+
+def bmm_cubic_noalloc(semiring, A, B, C, m, k, n, options=None, b_transposed=False,
+                      accumulate=False, stream=None):
+    """C = AB (or C ^= / |= AB) by the cubic method with B^T staged in the library's
+    fixed device array (no allocation; n * words(k) * 8 <= NOALLOC_SCRATCH_BYTES
+    unless B is given transposed)."""
+    flags = (FLAG_B_TRANSPOSED if b_transposed else 0) | (FLAG_ACCUMULATE if accumulate else 0)
+    fn = lambda *a: _c_noalloc(semiring, *a)
+    return _product(fn, A, B, C, m, k, n, options, flags, stream)
 
 
 def bmm_gf2_strassen_workspace(m, k, n, depth=-1, options=None, alt_basis_io=False):
