@@ -21,8 +21,13 @@ import time
 METRIC = "effective Pbop/s (2n^3/s), GF(2)+Boolean n=2^18: VALU vs int8-MFMA leaf"
 PEAK_MFMA_I8_TOPS = 5000.0        # dense int8 MFMA, ops/s (1 MAC = 2 ops)
 PEAK_MFMA_F4_TOPS = 10100.0       # dense fp4 (E2M1) MFMA
-# 256 CU * 128 lane-ops/clk (the fp32 vector rate: 157.3 TFLOP/s / 2) * 2.4 GHz * 32 bits
-# * 2 bit operations (AND and XOR/OR) per fused v_bitop3_b32
+# VALU bit-operation peaks (2 bit operations, the AND and the XOR/OR, on each of 32 bit
+# positions per fused v_bitop3_b32 lane-op), at 256 CUs and 2.4 GHz:
+#  - single issue: 4 SIMDs x 16 lanes = 64 lane-ops/clk/CU -> 2.517e15 bop/s;
+#  - gfx950 dual issue: two VALU instructions per SIMD per quad-cycle (counted by the
+#    SQ_ACTIVE_INST_VALU2 counter) = 128 lane-ops/clk/CU -> 5.033e15 bop/s, the rate the
+#    calibration kernel (bmm_calibrate_valu, bench --mode valu) measures.
+PEAK_VALU_SINGLE_TBOPS = 2516.6
 PEAK_VALU_FUSED_TBOPS = 5033.2
 # Bytes that one Boolean leaf launch at n = 2^18 moves between L2 and memory: rocprofv3
 # FETCH_SIZE and WRITE_SIZE of the int8 leaf with the tuned tile (7: 64 x 128, chunked
@@ -36,6 +41,62 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+class ClockSampler:
+    """The GPU's graphics clock (MHz), sampled every 20 ms on a host thread from the
+    SMU metrics table (amdsmi gpu_metrics: the average graphics clock, else the mean
+    of the per-XCD current clocks) while a region runs; mean_ghz() is None when the
+    metrics cannot be read."""
+
+    def __init__(self):
+        self.samples, self._stop, self._t, self._h, self._smi = [], None, None, None, None
+        try:
+            import amdsmi
+            amdsmi.amdsmi_init()
+            self._smi = amdsmi
+            self._h = amdsmi.amdsmi_get_processor_handles()[0]
+            self._read()
+        except Exception:
+            self._smi = None
+
+    def _read(self):
+        m = self._smi.amdsmi_get_gpu_metrics_info(self._h)
+        v = m.get("average_gfxclk_frequency")
+        if not isinstance(v, (int, float)) or v <= 0 or v >= 0xFFFF:
+            xs = [x for x in (m.get("current_gfxclks") or []) if isinstance(x, (int, float))
+                  and 0 < x < 0xFFFF]
+            v = sum(xs) / len(xs) if xs else None
+        return v
+
+    def __enter__(self):
+        import threading
+        self.samples = []
+        if self._smi is None:
+            return self
+        self._stop = threading.Event()
+
+        def run():
+            while not self._stop.is_set():
+                try:
+                    v = self._read()
+                    if v:
+                        self.samples.append(float(v))
+                except Exception:
+                    pass
+                self._stop.wait(0.02)
+        self._t = threading.Thread(target=run, daemon=True)
+        self._t.start()
+        return self
+
+    def __exit__(self, *exc):
+        if self._t:
+            self._stop.set()
+            self._t.join()
+            self._t = None
+
+    def mean_ghz(self):
+        return round(sum(self.samples) / len(self.samples) / 1e3, 3) if self.samples else None
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -47,26 +108,116 @@ def parse():
     ap.add_argument("--tune-file", default=None,
                     help="autotune table to load (default: the package's table for gfx950)")
     ap.add_argument("--depth-serial", type=int, default=-1)
+    ap.add_argument("--shift", type=int, default=-1,
+                    help="shifted leaf level of the GF(2) recursion: 0 off, 1 on, 2 on with "
+                         "8-byte loads, -1 the autotune table's choice")
     ap.add_argument("--tile", type=int, default=0,
                     help="tile variant of the timed leaf kind (0 = the autotune table's)")
     ap.add_argument("--no-valu", action="store_true", help="skip the VALU-leaf side step")
     ap.add_argument("--cpu-rows", type=int, default=256,
                     help="rows of the GF(2) product the oracle computes for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-rows-1core", type=int, default=16,
+                    help="rows of the GF(2) product the oracle computes on one thread")
+    ap.add_argument("--freivalds", type=int, default=2,
+                    help="Freivalds vectors checking the whole GF(2) product on the host")
     ap.add_argument("--leaf", choices=["mfma", "valu", "f4"], default="mfma",
                     help="leaf of the timed steps (mfma = int8 MFMA, f4 = E2M1 MFMA)")
     ap.add_argument("--no-f4", action="store_true", help="skip the fp4-leaf side step")
     ap.add_argument("--no-schemes", action="store_true",
                     help="skip timing the GF(2) recursion with the chaining and "
                          "Strassen-Winograd schemes")
-    ap.add_argument("--mode", choices=["step", "leaf", "cubic", "batched", "ooc", "tune"],
+    ap.add_argument("--mode", choices=["step", "leaf", "cubic", "batched", "ooc", "tune", "valu",
+                                       "small"],
                     default="step",
                     help="leaf: one Boolean leaf launch plus a copy of known size (for "
                          "profiler counters); batched: 4096 uneven products in one "
-                         "persistent launch; ooc: host-resident operands")
+                         "persistent launch; ooc: host-resident operands; valu: the VALU "
+                         "issue-rate calibration and the VALU leaf on both semirings; small: "
+                         "n = 2048 full products, graph-replayed, against the oracle")
     ap.add_argument("--problems", type=int, default=4096, help="batched mode: problem count")
     ap.add_argument("--block", type=int, default=1 << 17, help="ooc mode: block size (bits)")
     return ap.parse_args()
+
+
+def single_thread_seconds(fn):
+    """Seconds fn() takes with the OpenMP runtime held to one thread (the oracle's C
+    library runs its loops under OpenMP), or None if that runtime cannot be reached."""
+    import ctypes
+    try:
+        gomp = ctypes.CDLL("libgomp.so.1")
+        before = gomp.omp_get_max_threads()
+    except OSError:
+        return None
+    gomp.omp_set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        fn()
+        return time.perf_counter() - t0
+    finally:
+        gomp.omp_set_num_threads(before)
+
+
+def run_small(args, torch, np, bmm, bmmgen):
+    """The small plain-method workload: n = 2048, Bernoulli(1/2) bits, the GF(2) and
+    the Boolean product by the cubic method with each leaf kind, each timed as the mean
+    of `reps` launches replayed from one HIP graph (a single launch is microseconds) and
+    checked in full against the oracle, which is timed on all threads and on one."""
+    import oracle
+    n = args.n if args.n <= 8192 else 2048
+    reps = max(1000, args.steps)
+    seed = bmmgen.config_seed(0)
+    dev = torch.device("cuda:0")
+    A = bmmgen.fill_cpu(n, n, seed, bmmgen.TAG_A, bmmgen.Dist.half())
+    B = bmmgen.fill_cpu(n, n, seed, bmmgen.TAG_B, bmmgen.Dist.half())
+    Ad = torch.from_numpy(A.view(np.int64).copy()).to(dev)
+    Bd = torch.from_numpy(B.view(np.int64).copy()).to(dev)
+    BTd = torch.empty_like(Bd)
+    Cd = torch.empty_like(Ad)
+    bmm.bmm_transpose(Bd, BTd, n, n)
+    bops = 2.0 * n ** 3
+    out = {"mode": "small", "n": n, "reps_per_graph": reps}
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    for sname, sr in [("gf2", bmm.GF2), ("boolean", bmm.BOOLEAN)]:
+        c0 = time.perf_counter()
+        want = oracle.mul(A, B, n, n, sr)
+        c_all = time.perf_counter() - c0
+        c_one = single_thread_seconds(lambda: oracle.mul(A, B, n, n, sr))
+        out[f"{sname}_oracle"] = {"seconds_all_threads": round(c_all, 4), "threads": threads,
+                                  "seconds_one_thread": round(c_one, 4) if c_one else None,
+                                  "pbops_all_threads": round(bops / c_all / 1e15, 6)}
+        fn = bmm.bmm_gf2 if sr == bmm.GF2 else bmm.bmm_boolean
+        for lname, leaf in [("valu", bmm.LEAF_VALU), ("int8", bmm.LEAF_MFMA_I8),
+                            ("fp4", bmm.LEAF_MFMA_F4)]:
+            o = bmm.Options(leaf=leaf)
+            s_ = torch.cuda.Stream()
+            with torch.cuda.stream(s_):
+                fn(Ad, BTd, Cd, n, n, n, options=o, b_transposed=True, stream=s_.cuda_stream)
+                s_.synchronize()
+                g = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(g, stream=s_):
+                    for _ in range(reps):
+                        fn(Ad, BTd, Cd, n, n, n, options=o, b_transposed=True,
+                           stream=s_.cuda_stream)
+            torch.cuda.synchronize()
+            Cd.fill_(-1)
+            g.replay()  # warm-up replay
+            torch.cuda.synchronize()
+            ok = bool(np.array_equal(Cd.cpu().numpy().view(np.uint64), want))
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            g.replay()
+            e1.record()
+            torch.cuda.synchronize()
+            t = e0.elapsed_time(e1) / 1e3 / reps
+            _, tile = bmm.bmm_leaf_choice(sr, n, n, n, 1, o)
+            out[f"{sname}_{lname}"] = {"tile": tile, "seconds": t,
+                                       "pbops": round(bops / t / 1e15, 4),
+                                       "speedup_vs_oracle_all_threads": round(c_all / t, 1),
+                                       "verified_full": ok}
+            log(f"[bench] small {sname} {lname}: {out[f'{sname}_{lname}']}")
+            del g
+    print(json.dumps(out), flush=True)
 
 
 def run_batched(args, torch, np, bmm, bmmgen):
@@ -233,6 +384,91 @@ def run_cubic(args, torch, np, bmm, bmmgen):
     print(json.dumps(out), flush=True)
 
 
+def valu_calibration(bmm, rounds=1 << 21):
+    """bmm_calibrate_valu at 1-4 waves per SIMD: measured v_bitop3_b32 lane-ops per
+    core clock per CU, the waves' core clock and the aggregate bit-operation rate."""
+    out = {}
+    for w in (1, 2, 4, 8):
+        r = bmm.bmm_calibrate_valu(w, rounds)
+        out[str(w)] = {"lane_ops_per_clk_cu": round(r["lane_ops_per_clk_cu"], 2),
+                       "clock_ghz": round(r["clock_ghz"], 3),
+                       "seconds": round(r["seconds"], 5),
+                       "tbops": round(r["aggregate_bops"] / 1e12, 1)}
+        log(f"[bench] VALU calibration, {w} waves/SIMD: {out[str(w)]}")
+    return out
+
+
+def sustained_valu_tbops(cal):
+    """The highest calibrated v_bitop3_b32 issue rate (lane-ops per clock per CU, over
+    the waves-per-SIMD settings) as a bit-operation rate at 256 CUs and 2.4 GHz."""
+    best = max(v["lane_ops_per_clk_cu"] for v in cal.values())
+    return best * 256 * 2.4e9 * 64 / 1e12
+
+
+def valu_fracs(rate_tbops, sustained_tbops):
+    """A VALU leaf rate as fractions of the single-issue (64 lane-ops/clk/CU), the
+    dual-issue (128) and the measured sustained bit-operation peaks."""
+    return {"frac_single_issue": round(rate_tbops / PEAK_VALU_SINGLE_TBOPS, 4),
+            "frac_dual_issue": round(rate_tbops / PEAK_VALU_FUSED_TBOPS, 4),
+            "frac_sustained": round(rate_tbops / sustained_tbops, 4) if sustained_tbops else None}
+
+
+def run_valu(args, torch, np, bmm, bmmgen):
+    """The VALU roofline: the issue-rate calibration kernel, then the VALU leaf on
+    the cubic products at one size (GF(2) on Bernoulli(1/2) bits, Boolean on
+    Bernoulli(n^-1/2) bits), each as a fraction of the single-issue and the
+    dual-issue bit-operation peaks; 64 stratified rows of each checked."""
+    import oracle
+    n = args.n
+    cal = valu_calibration(bmm)
+    sustained = sustained_valu_tbops(cal)
+    out = {"mode": "valu", "n": n, "calibration": cal,
+           "peaks_tbops": {"single_issue_64_lanes": PEAK_VALU_SINGLE_TBOPS,
+                           "dual_issue_128_lanes": PEAK_VALU_FUSED_TBOPS,
+                           "sustained_measured": round(sustained, 1)}}
+    seed = bmmgen.config_seed(1)
+    dev = torch.device("cuda:0")
+    bops = 2.0 * n ** 3
+    rows = bmmgen.stratified_rows(n, 64, seed)
+    for sname, sr, dist in [("gf2", bmm.GF2, bmmgen.Dist.half()),
+                            ("boolean", bmm.BOOLEAN,
+                             bmmgen.Dist.pow2(max(1, (n.bit_length() - 1) // 2)))]:
+        A = torch.empty((n, n // 64), dtype=torch.int64, device=dev)
+        B = torch.empty_like(A)
+        BT = torch.empty_like(A)
+        C = torch.empty_like(A)
+        bmmgen.fill_tensor(A, n, n, seed, 0xA if sr == bmm.GF2 else 0x1A, dist)
+        bmmgen.fill_tensor(B, n, n, seed, 0xB if sr == bmm.GF2 else 0x1B, dist)
+        bmm.bmm_transpose(B, BT, n, n)
+        del B
+        fn = bmm.bmm_gf2 if sr == bmm.GF2 else bmm.bmm_boolean
+        o = bmm.Options(leaf=bmm.LEAF_VALU)
+        for _ in range(args.warmup):
+            fn(A, BT, C, n, n, n, options=o, b_transposed=True)
+        times = []
+        for _ in range(args.steps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn(A, BT, C, n, n, n, options=o, b_transposed=True)
+            e1.record()
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1) / 1e3)
+        t = sorted(times)[len(times) // 2]
+        got = C[rows].cpu().numpy().view(np.uint64)
+        Bh = bmmgen.fill_cpu(n, n, seed, 0xB if sr == bmm.GF2 else 0x1B, dist)
+        Ar = bmmgen.fill_rows_cpu(rows, n, seed, 0xA if sr == bmm.GF2 else 0x1A, dist)
+        want = oracle.rows(Ar, Bh, n, n, sr)
+        del Bh
+        rate = bops / t / 1e12
+        out[sname] = {"seconds": round(t, 5), "pbops": round(rate / 1e3, 4),
+                      **valu_fracs(rate, sustained),
+                      "verified_rows": len(rows), "verified": bool(np.array_equal(got, want))}
+        log(f"[bench] VALU leaf {sname}: {out[sname]}")
+        del A, BT, C
+        torch.cuda.empty_cache()
+    print(json.dumps(out), flush=True)
+
+
 def run_ooc(args, torch, np, bmm, bmmgen):
     """Products with A, B, C in page-locked host memory, streamed through HBM in
     b x b blocks (copies on their own streams, overlapped with compute).  GF(2)
@@ -319,6 +555,10 @@ def main():
         return run_batched(args, torch, np, bmm, bmmgen)
     if args.mode == "ooc":
         return run_ooc(args, torch, np, bmm, bmmgen)
+    if args.mode == "valu":
+        return run_valu(args, torch, np, bmm, bmmgen)
+    if args.mode == "small":
+        return run_small(args, torch, np, bmm, bmmgen)
 
     n = args.n
     nw = n // 64
@@ -349,7 +589,7 @@ def main():
         return bmm.Options(leaf=leaf, tile=args.tile if leaf == LEAF[args.leaf] else 0,
                            depth_serial=args.depth_serial,
                            depth_parallel=-1 if args.depth_serial < 0 else
-                           args.depth - args.depth_serial)
+                           args.depth - args.depth_serial, shift=args.shift)
 
     if args.mode == "leaf":
         bmm.bmm_transpose(Bb, BTb, n, n)
@@ -412,10 +652,11 @@ def main():
             out[f"strassen_leaf_{s_}"] = {"leaf": leaf, "tile": tile, "s": secs}
             log(f"[bench] tuned leaf {s_}^3 x64: leaf={leaf} tile={tile} {secs * 1e3:.2f} ms")
         # the depth tuner times the int8-MFMA leaf (the headline leaf)
-        d, dsel, secs = bmm.bmm_autotune_strassen(Ag, Bg, Cg, n, n, n, ws,
+        d, dsel, shift, secs = bmm.bmm_autotune_strassen(Ag, Bg, Cg, n, n, n, ws,
                                                   options=bmm.Options(leaf=bmm.LEAF_MFMA_I8))
-        out["strassen_depth"] = {"depth": d, "depth_serial": dsel, "seconds": secs}
-        log(f"[bench] tuned Strassen depth {d} (serial {dsel}) {secs:.3f} s")
+        out["strassen_depth"] = {"depth": d, "depth_serial": dsel, "shift": shift,
+                                 "seconds": secs}
+        log(f"[bench] tuned Strassen depth {d} (serial {dsel}, shift {shift}) {secs:.3f} s")
         bmm.bmm_autotune_save(tune_file)
         out["table"] = tune_file
         print(json.dumps(out), flush=True)
@@ -453,13 +694,19 @@ def main():
                       Cb.index_select(0, idx).cpu() if with_boolean else None)
 
     evs = [events() for _ in range(args.steps)]
+    clock = ClockSampler()
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        step(LEAF[args.leaf], evs[i])
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    with clock:
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            step(LEAF[args.leaf], evs[i])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+    step_sclk = clock.mean_ghz()
     keep(args.leaf)
+    # the headline GF(2) result, for Freivalds's check of the whole matrix at the end
+    C_head = (Cg.cpu().numpy().view(np.uint64)
+              if args.freivalds > 0 and not args.no_cpu_baseline else None)
     step_s = (t1 - t0) / args.steps
     gf2_s = sum(e[0].elapsed_time(e[1]) for e in evs) / args.steps / 1e3
     tr_s = sum(e[1].elapsed_time(e[2]) for e in evs) / args.steps / 1e3
@@ -471,8 +718,9 @@ def main():
     def side_step(name, peak_tbops):
         log(f"[bench] {name}-leaf step")
         e = events()
-        step(LEAF[name], e)
-        torch.cuda.synchronize()
+        with ClockSampler() as ck:
+            step(LEAF[name], e)
+            torch.cuda.synchronize()
         vg = e[0].elapsed_time(e[1]) / 1e3
         vb = e[2].elapsed_time(e[3]) / 1e3
         vt = e[0].elapsed_time(e[3]) / 1e3
@@ -480,12 +728,22 @@ def main():
         log(f"[bench] {name} step {vt:.3f} s (GF(2) {vg:.3f} s, Boolean {vb:.3f} s)")
         return {"step_s": round(vt, 4), "value": round(2 * bops / vt / 1e15, 4),
                 "gf2_strassen_s": round(vg, 4), "gf2_eff_pbops": round(bops / vg / 1e15, 4),
-                "boolean_s": round(vb, 4), "boolean_pbops": round(bops / vb / 1e15, 4),
-                "boolean_leaf_frac_of_peak": round(bops / vb / 1e12 / peak_tbops, 4)}
+                "boolean_leaf_s": round(vb, 4), "boolean_leaf_pbops": round(bops / vb / 1e15, 4),
+                "boolean_leaf_frac_of_peak": round(bops / vb / 1e12 / peak_tbops, 4),
+                "sclk_ghz": ck.mean_ghz()}
 
     valu = None
     if not args.no_valu and args.leaf != "valu":
         valu = side_step("valu", PEAK_VALU_FUSED_TBOPS)
+        # the VALU roofline three ways: 64 lane-ops/clk/CU (single issue), 128 (gfx950's
+        # dual issue) and the sustained issue rate the calibration kernel measures here
+        cal = valu_calibration(bmm)
+        sustained = sustained_valu_tbops(cal)
+        valu["boolean_leaf_fracs"] = valu_fracs(bops / valu["boolean_leaf_s"] / 1e12, sustained)
+        valu["issue_calibration"] = {
+            "sustained_lane_ops_per_clk_cu": max(v["lane_ops_per_clk_cu"] for v in cal.values()),
+            "sustained_tbops_at_2p4ghz": round(sustained, 1),
+            "by_waves_per_simd": cal}
     f4 = None
     if not args.no_f4 and args.leaf != "f4":
         f4 = side_step("f4", PEAK_MFMA_F4_TOPS)
@@ -521,6 +779,19 @@ def main():
     torch.cuda.synchronize()
     core_s = e[0].elapsed_time(e[1]) / 1e3
     log(f"[bench] GF(2) core (alternative basis in and out) {core_s:.3f} s")
+    # The Boolean leaf on dense operands (the GF(2) inputs, Bernoulli(1/2) bits) beside the
+    # sparse headline inputs: the matrix cores draw more power, and run at a lower clock,
+    # on dense bits.
+    e = events()
+    with ClockSampler() as ck:
+        e[0].record(stream)
+        bmm.bmm_boolean(Ag, BTb, Cb, n, n, n, options=opts(LEAF[args.leaf]), b_transposed=True)
+        e[1].record(stream)
+        torch.cuda.synchronize()
+    dense_s = e[0].elapsed_time(e[1]) / 1e3
+    dense = {"bits": "Bernoulli(1/2)", "leaf_s": round(dense_s, 4),
+             "pbops": round(bops / dense_s / 1e15, 4), "sclk_ghz": ck.mean_ghz()}
+    log(f"[bench] Boolean leaf on dense operands {dense_s:.3f} s")
 
     # Rows of both products, checked against the oracle; the GF(2) rows time the oracle.
     cpu = None
@@ -535,6 +806,20 @@ def main():
         c0 = time.perf_counter()
         want = oracle.rows(Ar, Bh, n, n, oracle.GF2)
         c1 = time.perf_counter()
+        log(f"[bench] oracle {c1 - c0:.2f} s for {len(rows_sample)} rows on {threads} threads")
+        # the same oracle on one thread, on fewer rows (the first of the sample)
+        r1 = max(1, min(args.cpu_rows_1core, len(rows_sample)))
+        one = single_thread_seconds(lambda: oracle.rows(Ar[:r1], Bh, n, n, oracle.GF2))
+        # Freivalds's check of the whole headline GF(2) product: (x^T A) B = x^T C
+        freivalds = None
+        if args.freivalds > 0 and C_head is not None:
+            Ah = bmmgen.fill_cpu(n, n, seed, bmmgen.TAG_A, bmmgen.Dist.half())
+            xs = bmmgen.freivalds_vectors(n, args.freivalds, seed)
+            f0 = time.perf_counter()
+            freivalds = all(oracle.freivalds(Ah, Bh, C_head, n, n, n, xs))
+            log(f"[bench] {args.freivalds} Freivalds vectors in {time.perf_counter() - f0:.1f} s:"
+                f" {freivalds}")
+            del Ah
         del Bh
         Bbh = bmmgen.fill_cpu(n, n, seed, 0x1B, bool_dist)
         Abr = bmmgen.fill_rows_cpu(rows_sample, n, seed, 0x1A, bool_dist)
@@ -542,6 +827,9 @@ def main():
         del Bbh
         # every variant's kept rows: the GF(2) product and (for leaf variants) the Boolean one
         verified = {"rows": len(rows_sample)}
+        if freivalds is not None:
+            verified["gf2_freivalds_vectors"] = args.freivalds
+            verified["gf2_freivalds"] = freivalds
         for name, (g, b) in kept.items():
             verified[name] = {"gf2": bool(np.array_equal(g.numpy().view(np.uint64), want))}
             if b is not None:
@@ -552,7 +840,11 @@ def main():
                "kind": "oracle",
                "sample": f"{len(rows_sample)} stratified rows of the GF(2) product at n={n} "
                          f"(2*rows*n^2 bit ops) in {c1 - c0:.2f} s"}
-        log(f"[bench] oracle {c1 - c0:.2f} s for {len(rows_sample)} rows; verified {verified}")
+        if one:
+            cpu["single_core"] = {"value": round(2.0 * r1 * n * n / one / 1e15, 9), "cores": 1,
+                                  "sample": f"{r1} of those rows on one thread in {one:.2f} s"}
+            log(f"[bench] oracle on one thread: {r1} rows in {one:.2f} s")
+        log(f"[bench] verified {verified}")
 
     value = 2 * bops / step_s / 1e15
     achieved = bops / leaf_s / 1e12  # TOP/s of the Boolean leaf launch
@@ -583,8 +875,12 @@ def main():
             "gf2_eff_pbops": round(bops / gf2_s / 1e15, 4),
             "gf2_core_s": round(core_s, 4),
             "gf2_core_eff_pbops": round(bops / core_s / 1e15, 4),
-            "boolean_s": round(leaf_s + tr_s, 4), "boolean_pbops": round(bops / leaf_s / 1e15, 4),
+            "boolean_s": round(leaf_s + tr_s, 4),
+            "boolean_pbops": round(bops / (leaf_s + tr_s) / 1e15, 4),
+            "boolean_leaf_s": round(leaf_s, 4), "boolean_leaf_pbops": round(bops / leaf_s / 1e15, 4),
         },
+        "sclk_ghz": step_sclk,
+        "boolean_dense_leaf": dense,
         "valu_leaf": valu,
         "f4_leaf": f4,
         "gf2_schemes": schemes,
@@ -593,7 +889,7 @@ def main():
                                + f" tile {leaf_tile} (Boolean cubic product, one launch per step)",
                      "achieved": round(achieved, 1), "peak": peak,
                      "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-                     "traffic": traffic},
+                     "traffic": traffic, "sclk_ghz_step": step_sclk},
         "cpu_baseline": cpu,
         "verified": verified,
     }

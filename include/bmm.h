@@ -81,9 +81,16 @@ typedef enum {
                                        alternative basis and C is left in it (the
                                        paper's timing convention, section 4.2) */
 #define BMM_FLAG_HOST_OPERANDS 0x8u /* A, B, C are page-locked host memory; blocks
-                                       stream through HBM (out-of-core pipeline) */
+                                       stream through HBM (out-of-core pipeline,
+                                       bmm_ooc); the call is then synchronous */
 #define BMM_FLAG_OOC_BLOCK_ORDER 0x10u /* out-of-core GF(2): stream the cubic block
                                           order instead of the host-level recursion */
+#define BMM_FLAG_INPLACE_BASIS 0x20u /* Strassen only: change A (and B when passed
+                                        transposed) to the alternative basis in place
+                                        and restore them afterwards, instead of
+                                        copying them into the workspace (the basis
+                                        changes are invertible in place, section 2.2
+                                        and section 3.6) */
 
 typedef struct {
   int leaf;           /* bmm_leaf; 0 = auto */
@@ -93,6 +100,12 @@ typedef struct {
   int64_t block;      /* out-of-core block size in bits (multiple of 64); 0 = auto */
   uint32_t flags;     /* BMM_FLAG_* */
   int scheme;         /* bmm_scheme of the GF(2) recursion; 0 = self-inverse */
+  int shift;          /* Strassen: the last parallel level shifted into the int8 leaf
+                         (section 3.15): 0 = off, 1 = on, 2 = on with 8-byte operand
+                         loads, -1 = the depth tuner's record for the shape and split
+                         (else off).  Applies where the leaf is int8, the scheme is not
+                         Winograd, depth_parallel >= 1 and a leaf's k is 2048 or 4096
+                         bits; elsewhere the plain leaf runs */
 } bmm_options;
 
 /* Fill *opt with the defaults (everything automatic, no flags). */
@@ -106,8 +119,14 @@ void bmm_options_init(bmm_options* opt);
  * hipMalloc on first use or growth, and synchronizes the device when it grows).
  * That buffer is shared by all such calls on a device, so calls on different
  * streams that may overlap must pass B^T (BMM_FLAG_B_TRANSPOSED).
+ * With BMM_FLAG_HOST_OPERANDS, A, B and C are page-locked host memory
+ * (hipHostMalloc) and the product runs as bmm_ooc in the cubic block order
+ * (opt->block sets the block size): the call waits for earlier work on
+ * hip_stream, then returns once C is complete; BMM_FLAG_ACCUMULATE and
+ * BMM_FLAG_B_TRANSPOSED are then BMM_E_UNSUPPORTED.
  * Errors: BMM_E_INVAL (negative size, null pointer with nonzero size, pitch too
- * small, C overlapping A or B), BMM_E_NOMEM, BMM_E_DEVICE. */
+ * small, C overlapping A or B, host memory not page-locked), BMM_E_NOMEM,
+ * BMM_E_DEVICE. */
 int bmm_gf2(const uint64_t* A, int64_t lda, const uint64_t* B, int64_t ldb, uint64_t* C,
             int64_t ldc, int64_t m, int64_t k, int64_t n, const bmm_options* opt,
             void* hip_stream);
@@ -129,17 +148,33 @@ int bmm_boolean(const uint64_t* A, int64_t lda, const uint64_t* B, int64_t ldb, 
  * bmm_gf2_strassen_workspace for the same arguments) holds the basis-changed
  * operands and the expanded levels; its contents on return are unspecified.
  * With BMM_FLAG_ALT_BASIS_IO the inputs are taken as A-hat, B-hat and C-hat is
- * returned (no basis changes).  With BMM_FLAG_ACCUMULATE the product is XORed
- * into C (into C-hat under BMM_FLAG_ALT_BASIS_IO; otherwise C is taken to the
- * alternative basis and back).
+ * returned (no basis changes; B given transposed is then read where it lies).
+ * With BMM_FLAG_ACCUMULATE the product is XORed into C (into C-hat under
+ * BMM_FLAG_ALT_BASIS_IO; otherwise C is taken to the alternative basis and back).
+ * With BMM_FLAG_INPLACE_BASIS the forward change is applied to the caller's A
+ * (and to B^T when B is passed transposed; an untransposed B is transposed into
+ * the workspace as always) and undone after the product, in stream order: the
+ * workspace shrinks by those copies, A and B hold alternative-basis words while
+ * the call's work runs (nothing else may read or write them until it finishes),
+ * and they hold their original words again once it has.  A and B must not
+ * overlap (BMM_E_INVAL).  Should a launch fail midway (BMM_E_DEVICE) their
+ * contents are unspecified.
+ * With BMM_FLAG_HOST_OPERANDS the operands are page-locked host memory and the
+ * product runs as bmm_ooc over GF(2) (host-level recursion levels above the
+ * in-HBM recursion; opt->block and opt->depth_* apply, `depth` and the
+ * workspace are not used; may be NULL): synchronous as for bmm_gf2;
+ * BMM_FLAG_ACCUMULATE, BMM_FLAG_B_TRANSPOSED and BMM_FLAG_ALT_BASIS_IO are then
+ * BMM_E_UNSUPPORTED.
  * Errors: as bmm_gf2, plus BMM_E_WORKSPACE. */
 int bmm_gf2_strassen(const uint64_t* A, int64_t lda, const uint64_t* B, int64_t ldb,
                      uint64_t* C, int64_t ldc, int64_t m, int64_t k, int64_t n, int depth,
                      void* workspace, size_t workspace_bytes, const bmm_options* opt,
                      void* hip_stream);
 
-/* Workspace bytes that bmm_gf2_strassen needs for these sizes and options, and
- * the depth split it will use (either out pointer may be NULL). */
+/* Workspace bytes that bmm_gf2_strassen needs for these sizes and options
+ * (opt->flags matter: BMM_FLAG_ALT_BASIS_IO, BMM_FLAG_INPLACE_BASIS and
+ * BMM_FLAG_B_TRANSPOSED decide which operands are staged), and the depth split
+ * it will use (either out pointer may be NULL). */
 int bmm_gf2_strassen_workspace(int64_t m, int64_t k, int64_t n, int depth,
                                const bmm_options* opt, size_t* bytes_out,
                                int* depth_serial_out, int* depth_parallel_out);
@@ -157,16 +192,35 @@ typedef struct {
 
 /* Many independent products of uneven sizes in one persistent launch
  * (workgroups pull work items of 2 x 2 wave tiles from per-XCD device-side
- * queues).  `problems` is a host
- * array.  Operands not given transposed are transposed into library scratch
- * first.  Equivalent to bmm_batched_plan_create + launch + destroy. */
+ * queues).  `problems` is a host array, read during the call only.
+ * The library keeps a plan per problem table (the pointers, sizes, pitches,
+ * semirings and b_transposed flags of every problem, with opt's leaf and tile,
+ * on the current device; at most 8, least recently used dropped first, all
+ * released by bmm_finalize): the first call with a table allocates its device
+ * problem table and a staging buffer for the right operands not given
+ * transposed, uploads the table and captures the launch sequence (the
+ * transposes into staging, the persistent kernel) into a hipGraph; every call,
+ * the first included, then replays that graph on hip_stream and returns without
+ * waiting.  The operands' contents are read when the work runs, so a table can
+ * be reused with new data in the same buffers.  Calls with the same table are
+ * ordered by the library (each waits, on the device, for the previous one, on
+ * whatever stream).  Inside stream capture the call enqueues the kernels into
+ * the caller's graph; its table's first call must come before, outside the
+ * capture (else BMM_E_UNSUPPORTED), and replays of such a graph must not overlap
+ * each other or another call with the same table.  New batched tuning records
+ * (bmm_autotune_batched, bmm_autotune_load) rebuild the plans on their next use. */
 int bmm_batched(const bmm_problem* problems, int64_t count, const bmm_options* opt,
                 void* hip_stream);
 
 /* A reusable batched plan: the problem table lives on the device, so a launch
  * is a fixed sequence of kernels that a caller may capture into a hipGraph and
  * replay.  All problems must have b_transposed set.  plan_create allocates
- * device memory (hipMalloc) and synchronizes; plan_launch only enqueues. */
+ * device memory (hipMalloc) and synchronizes; plan_launch only enqueues.
+ * Launches of one plan share its queue counters: outside stream capture each
+ * launch waits (on the device) for the plan's previous one, whatever the
+ * stream; launches captured into graphs are not ordered by the library, so
+ * replays of those graphs must not overlap each other or other launches of the
+ * plan (replay them on one stream). */
 int bmm_batched_plan_create(const bmm_problem* problems, int64_t count,
                             const bmm_options* opt, void** plan_out);
 int bmm_batched_plan_launch(void* plan, void* hip_stream);
@@ -252,8 +306,10 @@ int bmm_leaf_choice(int semiring, int64_t m, int64_t k, int64_t n, int64_t batch
  * BMM_LEAF_AUTO / tile 0; bmm_autotune_cubic is the batch-1 case;
  * bmm_autotune_set records an entry by hand.  Depth table:
  * bmm_autotune_strassen times bmm_gf2_strassen on the caller's operands for the
- * deepest four admissible depths (leaves >= 1024 bits), each with the fewest
- * depth-first levels whose workspace fits, and records the fastest for depth -1.
+ * deepest four admissible depths (leaves >= 1024 bits), each with the plain leaf
+ * and, where it applies, with the last level shifted into the leaf (shift 1 and 2),
+ * each with the fewest depth-first levels whose workspace fits, and records the
+ * fastest (depth, split, shift) for depth -1.
  * Both tables are per process and can be saved to / loaded from a text file. */
 int bmm_autotune_leaf(int semiring, int64_t m, int64_t k, int64_t n, int64_t batch,
                       int* leaf_out, int* tile_out, double* seconds_out);
@@ -264,7 +320,8 @@ int bmm_autotune_set(int semiring, int64_t m, int64_t k, int64_t n, int64_t batc
 int bmm_autotune_strassen(const uint64_t* A, int64_t lda, const uint64_t* B, int64_t ldb,
                           uint64_t* C, int64_t ldc, int64_t m, int64_t k, int64_t n,
                           void* workspace, size_t workspace_bytes, const bmm_options* opt,
-                          int* depth_out, int* depth_serial_out, double* seconds_out);
+                          int* depth_out, int* depth_serial_out, int* shift_out,
+                          double* seconds_out);
 int bmm_autotune_save(const char* path);
 int bmm_autotune_load(const char* path);
 
@@ -276,8 +333,9 @@ int bmm_autotune_load(const char* path);
  * rounds (a positive multiple of 4), with no memory traffic in the timed loop;
  * every wave reads the core-clock counter (s_memtime) and the constant-rate
  * counter before and after.  Outputs (any may be NULL):
- *   lane_ops_per_clk_cu: waves_per_simd x 64 lanes x 4 SIMDs x the median over
- *                        waves of instructions per core cycle;
+ *   lane_ops_per_clk_cu: all waves' lane operations (64 per instruction) over the
+ *                        launch's core cycles (HIP-event time x clock_ghz) and the
+ *                        CU count;
  *   clock_ghz:           median core clock of the waves;
  *   seconds:             the timed launch by HIP events;
  *   aggregate_bops:      2 x 32 bit operations per lane operation, all waves,

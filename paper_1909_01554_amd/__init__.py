@@ -35,6 +35,7 @@ FLAG_B_TRANSPOSED = 0x2
 FLAG_ALT_BASIS_IO = 0x4
 FLAG_HOST_OPERANDS = 0x8
 FLAG_OOC_BLOCK_ORDER = 0x10
+FLAG_INPLACE_BASIS = 0x20
 SCHEME_SELF_INVERSE, SCHEME_CHAINING, SCHEME_WINOGRAD = 0, 1, 2
 
 _STATUS = {0: "ok", -1: "invalid argument", -2: "unsupported", -3: "workspace too small",
@@ -62,14 +63,14 @@ _int = ctypes.c_int
 
 
 class Options(ctypes.Structure):
-    """bmm_options: leaf, tile, depth_serial, depth_parallel, block, flags, scheme."""
+    """bmm_options: leaf, tile, depth_serial, depth_parallel, block, flags, scheme, shift."""
     _fields_ = [("leaf", _int), ("tile", _int), ("depth_serial", _int),
                 ("depth_parallel", _int), ("block", _i64), ("flags", ctypes.c_uint32),
-                ("scheme", _int)]
+                ("scheme", _int), ("shift", _int)]
 
     def __init__(self, leaf=LEAF_AUTO, tile=0, depth_serial=-1, depth_parallel=-1, block=0,
-                 flags=0, scheme=0):
-        super().__init__(leaf, tile, depth_serial, depth_parallel, block, flags, scheme)
+                 flags=0, scheme=0, shift=-1):
+        super().__init__(leaf, tile, depth_serial, depth_parallel, block, flags, scheme, shift)
 
 
 class Problem(ctypes.Structure):
@@ -120,7 +121,8 @@ _c_tune_leaf = _sig("bmm_autotune_leaf", [_int, _i64, _i64, _i64, _i64, ctypes.P
 _c_tune_strassen = _sig("bmm_autotune_strassen",
                         [_vp, _i64, _vp, _i64, _vp, _i64, _i64, _i64, _i64, _vp,
                          ctypes.c_size_t, ctypes.POINTER(Options), ctypes.POINTER(_int),
-                         ctypes.POINTER(_int), ctypes.POINTER(ctypes.c_double)])
+                         ctypes.POINTER(_int), ctypes.POINTER(_int),
+                         ctypes.POINTER(ctypes.c_double)])
 _c_tune_save = _sig("bmm_autotune_save", [ctypes.c_char_p])
 _c_tune_load = _sig("bmm_autotune_load", [ctypes.c_char_p])
 _c_tiles = _sig("bmm_leaf_tiles", [_int, ctypes.POINTER(_int)])
@@ -149,6 +151,8 @@ def _stream(t, stream):
     if stream is not None:
         return ctypes.c_void_p(int(stream))
     import torch
+    if not t.is_cuda:  # host operands: the current device's current stream
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
     return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
 
 
@@ -232,16 +236,20 @@ def _product(fn, A, B, C, m, k, n, options, flags, stream):
     return C
 
 
-def bmm_gf2(A, B, C, m, k, n, options=None, b_transposed=False, accumulate=False, stream=None):
-    """C = AB (or C ^= AB) over GF(2) by the cubic method."""
-    flags = (FLAG_B_TRANSPOSED if b_transposed else 0) | (FLAG_ACCUMULATE if accumulate else 0)
+def bmm_gf2(A, B, C, m, k, n, options=None, b_transposed=False, accumulate=False, stream=None,
+            host_operands=False):
+    """C = AB (or C ^= AB) over GF(2) by the cubic method.  host_operands: A, B, C
+    are page-locked CPU tensors streamed through HBM (synchronous)."""
+    flags = ((FLAG_B_TRANSPOSED if b_transposed else 0) | (FLAG_ACCUMULATE if accumulate else 0)
+             | (FLAG_HOST_OPERANDS if host_operands else 0))
     return _product(_c_gf2, A, B, C, m, k, n, options, flags, stream)
 
 
 def bmm_boolean(A, B, C, m, k, n, options=None, b_transposed=False, accumulate=False,
-                stream=None):
+                stream=None, host_operands=False):
     """C = AB (or C |= AB) over the Boolean algebra by the cubic method."""
-    flags = (FLAG_B_TRANSPOSED if b_transposed else 0) | (FLAG_ACCUMULATE if accumulate else 0)
+    flags = ((FLAG_B_TRANSPOSED if b_transposed else 0) | (FLAG_ACCUMULATE if accumulate else 0)
+             | (FLAG_HOST_OPERANDS if host_operands else 0))
     return _product(_c_boolean, A, B, C, m, k, n, options, flags, stream)
 
 
@@ -255,9 +263,12 @@ def bmm_cubic_noalloc(semiring, A, B, C, m, k, n, options=None, b_transposed=Fal
     return _product(fn, A, B, C, m, k, n, options, flags, stream)
 
 
-def bmm_gf2_strassen_workspace(m, k, n, depth=-1, options=None, alt_basis_io=False):
+def bmm_gf2_strassen_workspace(m, k, n, depth=-1, options=None, alt_basis_io=False,
+                               b_transposed=False, inplace_basis=False):
     """(bytes, depth_serial, depth_parallel) of the Strassen product's workspace."""
-    o = _opts(options, FLAG_ALT_BASIS_IO if alt_basis_io else 0)
+    o = _opts(options, (FLAG_ALT_BASIS_IO if alt_basis_io else 0)
+              | (FLAG_B_TRANSPOSED if b_transposed else 0)
+              | (FLAG_INPLACE_BASIS if inplace_basis else 0))
     nbytes = ctypes.c_size_t(0)
     ds = _int(0)
     dp = _int(0)
@@ -267,17 +278,26 @@ def bmm_gf2_strassen_workspace(m, k, n, depth=-1, options=None, alt_basis_io=Fal
 
 
 def bmm_gf2_strassen(A, B, C, m, k, n, workspace, depth=-1, options=None, b_transposed=False,
-                     alt_basis_io=False, accumulate=False, stream=None):
-    """C = AB (or C ^= AB) over GF(2) by the self-inverse alternative-basis recursion."""
+                     alt_basis_io=False, accumulate=False, inplace_basis=False, stream=None,
+                     host_operands=False):
+    """C = AB (or C ^= AB) over GF(2) by the self-inverse alternative-basis recursion.
+    host_operands: A, B, C are page-locked CPU tensors, streamed through HBM by the
+    out-of-core pipeline (synchronous; workspace and depth are not used)."""
     o = _opts(options, (FLAG_B_TRANSPOSED if b_transposed else 0)
               | (FLAG_ALT_BASIS_IO if alt_basis_io else 0)
-              | (FLAG_ACCUMULATE if accumulate else 0))
-    _operands(A, B, C, m, k, n, b_transposed)
-    if not _is_tensor(workspace) or not workspace.is_cuda or not workspace.is_contiguous():
-        raise ValueError("the workspace must be a contiguous GPU tensor")
-    nbytes = workspace.numel() * workspace.element_size()
+              | (FLAG_ACCUMULATE if accumulate else 0)
+              | (FLAG_INPLACE_BASIS if inplace_basis else 0)
+              | (FLAG_HOST_OPERANDS if host_operands else 0))
+    host = bool(o.flags & FLAG_HOST_OPERANDS)
+    _operands(A, B, C, m, k, n, b_transposed, device=not host)
+    if host:
+        ws, nbytes = None, 0
+    else:
+        if not _is_tensor(workspace) or not workspace.is_cuda or not workspace.is_contiguous():
+            raise ValueError("the workspace must be a contiguous GPU tensor")
+        ws, nbytes = _ptr(workspace), workspace.numel() * workspace.element_size()
     _check(_c_strassen(_ptr(A), _ld(A), _ptr(B), _ld(B), _ptr(C), _ld(C), m, k, n, depth,
-                       _ptr(workspace), nbytes, ctypes.byref(o), _stream(C, stream)))
+                       ws, nbytes, ctypes.byref(o), _stream(C, stream)))
     return C
 
 
@@ -457,17 +477,22 @@ def bmm_autotune_leaf(semiring, m, k, n, batch=1):
 
 
 def bmm_autotune_strassen(A, B, C, m, k, n, workspace, options=None):
-    """Time the admissible Strassen depths on these operands; returns
-    (depth, depth_serial, seconds) and records them for depth -1."""
+    """Time the admissible Strassen depths (plain and shifted leaf level) on these
+    operands; returns (depth, depth_serial, shift, seconds) and records them for
+    depth -1."""
     o = _opts(options, 0)
+    _operands(A, B, C, m, k, n, False)
+    if not _is_tensor(workspace) or not workspace.is_cuda or not workspace.is_contiguous():
+        raise ValueError("the workspace must be a contiguous GPU tensor")
     d = _int(0)
     ds = _int(0)
+    sh = _int(0)
     secs = ctypes.c_double(0.0)
     nbytes = workspace.numel() * workspace.element_size()
     _check(_c_tune_strassen(_ptr(A), _ld(A), _ptr(B), _ld(B), _ptr(C), _ld(C), m, k, n,
                             _ptr(workspace), nbytes, ctypes.byref(o), ctypes.byref(d),
-                            ctypes.byref(ds), ctypes.byref(secs)))
-    return d.value, ds.value, secs.value
+                            ctypes.byref(ds), ctypes.byref(sh), ctypes.byref(secs)))
+    return d.value, ds.value, sh.value, secs.value
 
 
 def bmm_autotune_set(semiring, m, k, n, leaf, tile, batch=1):

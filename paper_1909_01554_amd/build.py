@@ -14,7 +14,7 @@ FLAGS = ["-O3", "--offload-arch=gfx950", "-fPIC", "-std=c++17", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(os.path.dirname(HERE), "include")]
 
-SOURCES = ["leaf_mfma.hip", "leaf_mfma_lds.hip", "leaf_valu.hip", "transpose.hip", "basis.hip", "combine.hip",
+SOURCES = ["leaf_mfma.hip", "leaf_mfma_lds.hip", "leaf_shift.hip", "leaf_valu.hip", "transpose.hip", "basis.hip", "combine.hip",
            "batched.hip", "calib.hip", "noalloc.hip", "api.cpp", "batched_api.cpp", "ooc.cpp"]
 
 

@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -118,10 +119,13 @@ struct TuneVal {
   int tile[4] = {0, 0, 0, 0};
 };
 std::map<TuneKey, TuneVal> g_tune;
-// Strassen (depth, serial depth) per shape, from bmm_autotune_strassen.
-std::map<std::tuple<int64_t, int64_t, int64_t>, std::pair<int, int>> g_depth;
+// Strassen (depth, serial depth, shifted leaf level) per shape, from bmm_autotune_strassen.
+std::map<std::tuple<int64_t, int64_t, int64_t>, std::tuple<int, int, int>> g_depth;
 // Batched plans: (problem count, floor(log2(total ops))) -> (leaf, tile, workgroups per CU).
 std::map<std::pair<int64_t, int>, std::tuple<int, int, int>> g_batched;
+// Bumped whenever g_batched changes, so cached batched plans built from older records
+// are rebuilt.
+std::atomic<uint64_t> g_batched_gen{0};
 
 int ops_bucket(double ops) {
   int b = 0;
@@ -250,12 +254,30 @@ int cubic_product(int semiring, const uint64_t* A, int64_t lda, const uint64_t* 
 
 namespace {
 
+// Host-resident operands (BMM_FLAG_HOST_OPERANDS) go through the out-of-core
+// pipeline, synchronously: earlier work on the caller's stream finishes first (it may
+// produce A or B), and C is complete on return.  cubic = 1 keeps the cubic method
+// for GF(2) (block order, no recursion levels).
+int host_product(int semiring, const uint64_t* A, int64_t lda, const uint64_t* B,
+                 int64_t ldb, uint64_t* C, int64_t ldc, int64_t m, int64_t k, int64_t n,
+                 bmm_options o, void* stream, bool cubic) {
+  if (o.flags & (BMM_FLAG_ACCUMULATE | BMM_FLAG_B_TRANSPOSED | BMM_FLAG_ALT_BASIS_IO))
+    return fail(BMM_E_UNSUPPORTED, "host operands: accumulation, B passed transposed and "
+                "alternative-basis input are not supported out of core");
+  if (cubic) {
+    o.flags |= BMM_FLAG_OOC_BLOCK_ORDER;
+    o.depth_serial = o.depth_parallel = 0;
+  }
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream), "hipStreamSynchronize");
+  return bmm_ooc(semiring, A, lda, B, ldb, C, ldc, m, k, n, o.block, &o, nullptr);
+}
+
 int cubic(int semiring, const uint64_t* A, int64_t lda, const uint64_t* B, int64_t ldb,
           uint64_t* C, int64_t ldc, int64_t m, int64_t k, int64_t n, const bmm_options* opt,
           void* stream) {
   const bmm_options o = opt ? *opt : defaults();
   if (o.flags & BMM_FLAG_HOST_OPERANDS)
-    return fail(BMM_E_UNSUPPORTED, "host operands: use the out-of-core entry (bmm_ooc)");
+    return host_product(semiring, A, lda, B, ldb, C, ldc, m, k, n, o, stream, true);
   return cubic_product(semiring, A, lda, B, ldb, C, ldc, m, k, n, opt, stream, nullptr);
 }
 
@@ -266,6 +288,8 @@ struct Level {
 
 struct StrassenPlan {
   int depth = 0, ds = 0, dp = 0;
+  int shift = 0;  // 0: plain leaf; 1, 2: last parallel level inside the int8 leaf
+                  // (2: with 8-byte operand loads)
   int scheme = BMM_SCHEME_SELF_INVERSE;
   int64_t m = 0, kw = 0, n = 0, nw = 0;
   size_t ahat = 0, bhat = 0;
@@ -277,9 +301,30 @@ struct StrassenPlan {
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// alt_io: A is used in place (already in the alternative basis), so no copy of it
-// is planned.  stage_b = false: the caller supplies B^T in the alternative basis.
-int make_plan(int64_t m, int64_t k, int64_t n, int depth, const bmm_options& o, bool alt_io,
+// Whether (depth, ds) is the depth tuner's record for this shape (its shift choice
+// belongs to that split only).
+bool depth_is_tuned(int64_t m, int64_t k, int64_t n, int depth, int ds) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  auto it = g_depth.find({m, k, n});
+  return it != g_depth.end() && std::get<0>(it->second) == depth &&
+         std::get<1>(it->second) == ds;
+}
+
+// Which operands the product stages in its workspace: a copy of A unless A is
+// read where it lies (already in the alternative basis, or changed in place and
+// restored); B^T unless B is passed transposed and read where it lies.
+struct Staging {
+  bool a, b;
+};
+Staging staging_of(const bmm_options& o) {
+  const bool alt = (o.flags & BMM_FLAG_ALT_BASIS_IO) != 0;
+  const bool inplace = (o.flags & BMM_FLAG_INPLACE_BASIS) != 0;
+  const bool b_t = (o.flags & BMM_FLAG_B_TRANSPOSED) != 0;
+  return Staging{!alt && !inplace, !b_t || (!alt && !inplace)};
+}
+
+// stage_a / stage_b: plan room for a copy of A / for B^T (see Staging).
+int make_plan(int64_t m, int64_t k, int64_t n, int depth, const bmm_options& o, bool stage_a,
               StrassenPlan* plan, bool stage_b = true) {
   if (m < 0 || k < 0 || n < 0) return fail(BMM_E_INVAL, "negative size");
   if (depth < -1 || depth > 12) return fail(BMM_E_INVAL, "depth %d out of range", depth);
@@ -291,14 +336,11 @@ int make_plan(int64_t m, int64_t k, int64_t n, int depth, const bmm_options& o, 
   P.kw = words_of(k);
   P.n = n;
   P.nw = words_of(n);
-  int tuned_ds = -1;
+  int tuned_ds = -1, tuned_shift = 0;
   if (depth == -1) {
     std::lock_guard<std::mutex> lock(g_mu);
     auto it = g_depth.find({m, k, n});
-    if (it != g_depth.end()) {
-      depth = it->second.first;
-      tuned_ds = it->second.second;
-    }
+    if (it != g_depth.end()) std::tie(depth, tuned_ds, tuned_shift) = it->second;
   }
   if (depth == -1) {
     // largest depth keeping every leaf dimension >= 2048 bits (at most 8 levels): the
@@ -335,8 +377,23 @@ int make_plan(int64_t m, int64_t k, int64_t n, int depth, const bmm_options& o, 
     return fail(BMM_E_INVAL, "depth_serial %d + depth_parallel %d != depth %d", ds, dp, depth);
   P.ds = ds;
   P.dp = dp;
+  // the shifted leaf level: the option, else the tuned choice for this shape (with the
+  // tuned depth split only), else off; it needs a parallel level, the int8 leaf and a
+  // leaf shape the kernel covers, else the plain leaf runs
+  if (o.shift < -1 || o.shift > 2) return fail(BMM_E_INVAL, "shift %d out of range", o.shift);
+  int sh = o.shift >= 0 ? o.shift : (depth_is_tuned(m, k, n, depth, ds) ? tuned_shift : 0);
+  if (sh > 0) {
+    const int64_t u = (int64_t)1 << depth;
+    int lf = 0, tl = 0;
+    int64_t leaves = 1;
+    for (int i = 0; i < dp; ++i) leaves *= 7;
+    pick_leaf(BMM_GF2, m / u, k / u, n / u, leaves, o, &lf, &tl);
+    if (dp < 1 || lf != BMM_LEAF_MFMA_I8 || !leaf_shift_supported(o.scheme, m / u, k / u, n / u))
+      sh = 0;
+  }
+  P.shift = sh;
   size_t off = 0;
-  if (!alt_io) {
+  if (stage_a) {
     P.ahat = off;
     off = align_up(off + (size_t)m * P.kw * 8);
   }
@@ -355,7 +412,7 @@ int make_plan(int64_t m, int64_t k, int64_t n, int depth, const bmm_options& o, 
     off = align_up(off + (size_t)7 * M * NW * 8);
     P.serial.push_back(L);
   }
-  int left = dp, lvl = ds;
+  int left = dp - (P.shift ? 1 : 0), lvl = ds;  // levels expanded in HBM
   int64_t inst = 1;
   while (left > 0) {
     const int step = left >= 2 ? 2 : 1;
@@ -422,9 +479,20 @@ struct StrassenRun {
     const int64_t M = p.m >> lvl, N = p.n >> lvl, NW = p.nw >> lvl;
     uint64_t* leafQ = p.par.empty() ? Q : at(p.par.back().Q);
     const int64_t ldLQ = p.par.empty() ? ldQ : NW;
-    LeafBatch lb{curT, pitchT, strideT, curS, pitchS, strideS, leafQ, ldLQ, M * NW,
-                 M, (p.kw >> lvl) * 64, N, inst, p.par.empty() ? acc : 0};
-    BMM_TRY(run_leaf(BMM_GF2, leaf, tile, lb, s));
+    if (p.shift) {
+      // the last level inside the leaf: the instances at this level are the parents
+      // of the seven products each, their results this level's Q
+      const int64_t cM = M >> 1, cN = N >> 1, cK = ((p.kw >> lvl) >> 1) * 64;
+      if (!leaf_shift_fits(cM, pitchT) || !leaf_shift_fits(cN, pitchS))
+        return fail(BMM_E_UNSUPPORTED, "shifted leaf: operand pitches too large");
+      ShiftBatch sb{curT, pitchT, strideT, curS, pitchS, strideS, leafQ, ldLQ, M * NW,
+                    cM, cK, cN, inst, p.par.empty() ? acc : 0};
+      HIP_TRY(launch_leaf_shift(p.scheme, sb, p.shift == 2 ? 1 : 2, s), "shifted leaf");
+    } else {
+      LeafBatch lb{curT, pitchT, strideT, curS, pitchS, strideS, leafQ, ldLQ, M * NW,
+                   M, (p.kw >> lvl) * 64, N, inst, p.par.empty() ? acc : 0};
+      BMM_TRY(run_leaf(BMM_GF2, leaf, tile, lb, s));
+    }
     // compress back up
     for (int i = (int)p.psteps.size() - 1; i >= 0; --i) {
       const int step = p.psteps[i];
@@ -484,6 +552,7 @@ void bmm_options_init(bmm_options* opt) {
   opt->block = 0;
   opt->flags = 0;
   opt->scheme = BMM_SCHEME_SELF_INVERSE;
+  opt->shift = -1;
 }
 
 int bmm_gf2(const uint64_t* A, int64_t lda, const uint64_t* B, int64_t ldb, uint64_t* C,
@@ -503,7 +572,8 @@ int bmm_gf2_strassen_workspace(int64_t m, int64_t k, int64_t n, int depth,
                                int* depth_serial_out, int* depth_parallel_out) {
   const bmm_options o = opt ? *opt : defaults();
   StrassenPlan P;
-  BMM_TRY(make_plan(m, k, n, depth, o, (o.flags & BMM_FLAG_ALT_BASIS_IO) != 0, &P));
+  const Staging st = staging_of(o);
+  BMM_TRY(make_plan(m, k, n, depth, o, st.a, &P, st.b));
   if (bytes_out) *bytes_out = P.bytes;
   if (depth_serial_out) *depth_serial_out = P.ds;
   if (depth_parallel_out) *depth_parallel_out = P.dp;
@@ -516,14 +586,19 @@ int bmm_gf2_strassen(const uint64_t* A, int64_t lda, const uint64_t* B, int64_t 
                      void* hip_stream) {
   const bmm_options o = opt ? *opt : defaults();
   if (o.flags & BMM_FLAG_HOST_OPERANDS)
-    return fail(BMM_E_UNSUPPORTED, "host operands: use the out-of-core entry (bmm_ooc)");
+    return host_product(BMM_GF2, A, lda, B, ldb, C, ldc, m, k, n, o, hip_stream, false);
   const bool b_t = (o.flags & BMM_FLAG_B_TRANSPOSED) != 0;
   const bool alt = (o.flags & BMM_FLAG_ALT_BASIS_IO) != 0;
+  const bool inplace = !alt && (o.flags & BMM_FLAG_INPLACE_BASIS) != 0;
   const int acc = (o.flags & BMM_FLAG_ACCUMULATE) ? 1 : 0;
   BMM_TRY(validate_product(A, lda, B, ldb, C, ldc, m, k, n, b_t));
+  const Staging st = staging_of(o);
   StrassenPlan P;
-  BMM_TRY(make_plan(m, k, n, depth, o, alt, &P));
+  BMM_TRY(make_plan(m, k, n, depth, o, st.a, &P, st.b));
   if (m == 0 || n == 0) return BMM_OK;
+  if (inplace && k > 0 &&
+      overlaps(extent(A, m, lda, P.kw), b_t ? extent(B, n, ldb, P.kw) : extent(B, k, ldb, P.nw)))
+    return fail(BMM_E_INVAL, "in-place basis changes need A and B not to overlap");
   hipStream_t s = (hipStream_t)hip_stream;
   if (k == 0) return acc ? BMM_OK : check_hip(launch_zero(C, ldc, m, P.nw, s), "zero");
   if (!workspace || workspace_bytes < P.bytes)
@@ -537,21 +612,33 @@ int bmm_gf2_strassen(const uint64_t* A, int64_t lda, const uint64_t* B, int64_t 
       overlaps(ew, b_t ? extent(B, n, ldb, P.kw) : extent(B, k, ldb, P.nw)))
     return fail(BMM_E_INVAL, "workspace overlaps an operand");
   char* ws = static_cast<char*>(workspace);
-  uint64_t* BT = reinterpret_cast<uint64_t*>(ws + P.bhat);
-  if (b_t)
-    HIP_TRY(launch_copy(B, ldb, BT, P.kw, n, P.kw, s), "copy B^T");
-  else
-    HIP_TRY(launch_transpose(B, ldb, 0, BT, P.kw, 0, k, n, 1, s), "transpose B");
-  const uint64_t* T0 = A;
-  int64_t ldT0 = lda;
-  if (!alt) {
-    uint64_t* Ah = reinterpret_cast<uint64_t*>(ws + P.ahat);
-    HIP_TRY(launch_copy(A, lda, Ah, P.kw, m, P.kw, s), "copy A");
-    HIP_TRY(launch_basis(Ah, P.kw, 0, m, P.kw, 1, P.depth, 0, s, P.scheme, 0), "basis A");
-    HIP_TRY(launch_basis(BT, P.kw, 0, n, P.kw, 1, P.depth, 0, s, P.scheme, 1), "basis B");
-    T0 = Ah;
-    ldT0 = P.kw;
+  // B^T: staged in the workspace (transposed, or copied when it will be changed), or
+  // read where it lies (alternative-basis input, or changed in place)
+  uint64_t* BT = const_cast<uint64_t*>(B);
+  int64_t ldbt = ldb;
+  if (st.b) {
+    BT = reinterpret_cast<uint64_t*>(ws + P.bhat);
+    ldbt = P.kw;
+    if (b_t)
+      HIP_TRY(launch_copy(B, ldb, BT, P.kw, n, P.kw, s), "copy B^T");
+    else
+      HIP_TRY(launch_transpose(B, ldb, 0, BT, P.kw, 0, k, n, 1, s), "transpose B");
   }
+  uint64_t* Ah = const_cast<uint64_t*>(A);
+  int64_t ldah = lda;
+  if (st.a) {
+    Ah = reinterpret_cast<uint64_t*>(ws + P.ahat);
+    ldah = P.kw;
+    HIP_TRY(launch_copy(A, lda, Ah, P.kw, m, P.kw, s), "copy A");
+  }
+  if (!alt) {
+    // forward changes (eq. mb-fwdbasisrecurrence / ab-fwdbasisrecurrence), in the
+    // workspace copies or in the caller's A and B^T (BMM_FLAG_INPLACE_BASIS)
+    HIP_TRY(launch_basis(Ah, ldah, 0, m, P.kw, 1, P.depth, 0, s, P.scheme, 0), "basis A");
+    HIP_TRY(launch_basis(BT, ldbt, 0, n, P.kw, 1, P.depth, 0, s, P.scheme, 1), "basis B");
+  }
+  const uint64_t* T0 = Ah;
+  const int64_t ldT0 = ldah;
   int leaf, tile;
   const int64_t u = (int64_t)1 << P.depth;
   int64_t leaves = 1;
@@ -562,8 +649,17 @@ int bmm_gf2_strassen(const uint64_t* A, int64_t lda, const uint64_t* B, int64_t 
   // alternative basis and back (chi^-1 is chi itself for the self-inverse design
   // and the forward change for the chaining one).
   if (!alt && acc) HIP_TRY(to_alt_basis(C, ldc, m, P.nw, P.depth, P.scheme, s), "basis C");
-  BMM_TRY(run.solve(0, T0, ldT0, BT, P.kw, C, ldc, acc));
+  BMM_TRY(run.solve(0, T0, ldT0, BT, ldbt, C, ldc, acc));
   if (!alt) HIP_TRY(launch_basis(C, ldc, 0, m, P.nw, 1, P.depth, 1, s, P.scheme), "basis C");
+  if (inplace) {
+    // restore the caller's operands: the self-inverse change is an involution (its
+    // forward change again), the chaining change is undone by its inverse (section 2.3)
+    const int undo = P.scheme == BMM_SCHEME_CHAINING ? 1 : 0;
+    if (!st.a)
+      HIP_TRY(launch_basis(Ah, ldah, 0, m, P.kw, 1, P.depth, undo, s, P.scheme, 0), "restore A");
+    if (!st.b)
+      HIP_TRY(launch_basis(BT, ldbt, 0, n, P.kw, 1, P.depth, undo, s, P.scheme, 1), "restore B");
+  }
   return BMM_OK;
 }
 
@@ -582,7 +678,10 @@ bool batched_tuned(int64_t count, double ops, int* leaf, int* tile, int* wg_per_
 void batched_tune_set(int64_t count, double ops, int leaf, int tile, int wg_per_cu) {
   std::lock_guard<std::mutex> lock(g_mu);
   g_batched[{count, ops_bucket(ops)}] = {leaf, tile, wg_per_cu};
+  ++g_batched_gen;
 }
+
+uint64_t batched_tune_generation() { return g_batched_gen.load(); }
 
 void choose_leaf(int semiring, int64_t m, int64_t k, int64_t n, int64_t batch,
                  const bmm_options& o, int* leaf, int* tile) {
@@ -601,7 +700,7 @@ hipError_t to_alt_basis(uint64_t* C, int64_t ldc, int64_t rows, int64_t words, i
 int strassen_alt_plan(int64_t m, int64_t k, int64_t n, int depth, const bmm_options& o,
                       size_t* bytes, int* depth_out) {
   StrassenPlan P;
-  BMM_TRY(make_plan(m, k, n, depth, o, true, &P, false));
+  BMM_TRY(make_plan(m, k, n, depth, o, false, &P, false));
   *bytes = P.bytes;
   *depth_out = P.depth;
   return BMM_OK;
@@ -611,7 +710,7 @@ int strassen_alt(const uint64_t* Ahat, int64_t lda, const uint64_t* BThat, int64
                  uint64_t* C, int64_t ldc, int64_t m, int64_t k, int64_t n, int depth,
                  void* ws, size_t bytes, const bmm_options& o, int accumulate, hipStream_t s) {
   StrassenPlan P;
-  BMM_TRY(make_plan(m, k, n, depth, o, true, &P, false));
+  BMM_TRY(make_plan(m, k, n, depth, o, false, &P, false));
   if (bytes < P.bytes) return fail(BMM_E_WORKSPACE, "workspace of %zu bytes needed", P.bytes);
   if (m == 0 || n == 0 || (k == 0 && accumulate)) return BMM_OK;
   if (k == 0) return check_hip(launch_zero(C, ldc, m, P.nw, s), "zero");
@@ -841,7 +940,8 @@ int bmm_autotune_cubic(int semiring, int64_t m, int64_t k, int64_t n, int* leaf_
 int bmm_autotune_strassen(const uint64_t* A, int64_t lda, const uint64_t* B, int64_t ldb,
                           uint64_t* C, int64_t ldc, int64_t m, int64_t k, int64_t n,
                           void* workspace, size_t workspace_bytes, const bmm_options* opt,
-                          int* depth_out, int* depth_serial_out, double* seconds_out) {
+                          int* depth_out, int* depth_serial_out, int* shift_out,
+                          double* seconds_out) {
   const bmm_options o = opt ? *opt : defaults();
   int dmax = 0;
   while (dmax < 10) {
@@ -854,36 +954,44 @@ int bmm_autotune_strassen(const uint64_t* A, int64_t lda, const uint64_t* B, int
   (void)hipEventCreate(&e0);
   (void)hipEventCreate(&e1);
   double best = 1e30;
-  int best_d = -1, best_ds = -1, rc = BMM_OK, tried = 0;
+  int best_d = -1, best_ds = -1, best_sh = 0, rc = BMM_OK, tried = 0;
   for (int d = dmax; d >= std::max(0, dmax - 3); --d) {
-    for (int ds = 0; ds <= d; ++ds) {
-      bmm_options t = o;
-      t.depth_serial = ds;
-      t.depth_parallel = d - ds;
-      size_t need = 0;
-      if (bmm_gf2_strassen_workspace(m, k, n, d, &t, &need, nullptr, nullptr) != BMM_OK) continue;
-      if (need > workspace_bytes) continue;  // more breadth-first levels than memory allows
-      rc = bmm_gf2_strassen(A, lda, B, ldb, C, ldc, m, k, n, d, workspace, workspace_bytes, &t,
-                            nullptr);
-      if (rc != BMM_OK) break;
-      (void)hipEventRecord(e0, nullptr);
-      rc = bmm_gf2_strassen(A, lda, B, ldb, C, ldc, m, k, n, d, workspace, workspace_bytes, &t,
-                            nullptr);
-      (void)hipEventRecord(e1, nullptr);
-      if (rc != BMM_OK) break;
-      if (hipEventSynchronize(e1) != hipSuccess) {
-        rc = check_hip(hipGetLastError(), "autotune sync");
-        break;
+    // the plain leaf, then the shifted leaf level with 16-byte and with 8-byte operand
+    // loads, each with the fewest depth-first levels whose workspace fits
+    for (int sh = 0; sh <= 2 && rc == BMM_OK; ++sh) {
+      for (int ds = 0; ds <= d; ++ds) {
+        bmm_options t = o;
+        t.depth_serial = ds;
+        t.depth_parallel = d - ds;
+        t.shift = sh;
+        StrassenPlan P;
+        const Staging st = staging_of(t);
+        if (make_plan(m, k, n, d, t, st.a, &P, st.b) != BMM_OK) continue;
+        if (P.shift != sh) break;  // this shift does not apply at this depth
+        if (P.bytes > workspace_bytes) continue;  // more breadth-first levels than memory allows
+        rc = bmm_gf2_strassen(A, lda, B, ldb, C, ldc, m, k, n, d, workspace, workspace_bytes,
+                              &t, nullptr);
+        if (rc != BMM_OK) break;
+        (void)hipEventRecord(e0, nullptr);
+        rc = bmm_gf2_strassen(A, lda, B, ldb, C, ldc, m, k, n, d, workspace, workspace_bytes,
+                              &t, nullptr);
+        (void)hipEventRecord(e1, nullptr);
+        if (rc != BMM_OK) break;
+        if (hipEventSynchronize(e1) != hipSuccess) {
+          rc = check_hip(hipGetLastError(), "autotune sync");
+          break;
+        }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        ++tried;
+        if (ms * 1e-3 < best) {
+          best = ms * 1e-3;
+          best_d = d;
+          best_ds = ds;
+          best_sh = sh;
+        }
+        break;  // the fewest serial levels that fit is the candidate for this depth
       }
-      float ms = 0.f;
-      (void)hipEventElapsedTime(&ms, e0, e1);
-      ++tried;
-      if (ms * 1e-3 < best) {
-        best = ms * 1e-3;
-        best_d = d;
-        best_ds = ds;
-      }
-      break;  // the fewest serial levels that fit is the candidate for this depth
     }
     if (rc != BMM_OK) break;
   }
@@ -893,10 +1001,11 @@ int bmm_autotune_strassen(const uint64_t* A, int64_t lda, const uint64_t* B, int
   if (!tried) return fail(BMM_E_WORKSPACE, "no Strassen depth fits the workspace");
   {
     std::lock_guard<std::mutex> lock(g_mu);
-    g_depth[{m, k, n}] = {best_d, best_ds};
+    g_depth[{m, k, n}] = {best_d, best_ds, best_sh};
   }
   if (depth_out) *depth_out = best_d;
   if (depth_serial_out) *depth_serial_out = best_ds;
+  if (shift_out) *shift_out = best_sh;
   if (seconds_out) *seconds_out = best;
   return BMM_OK;
 }
@@ -908,7 +1017,7 @@ int bmm_autotune_save(const char* path) {
   std::lock_guard<std::mutex> lock(g_mu);
   f << "# bmm autotune table\n"
        "# leaf semiring m k n batch_bucket best_leaf tile_valu tile_mfma_i8 tile_mfma_f4\n"
-       "# depth m k n depth depth_serial\n"
+       "# depth m k n depth depth_serial shift\n"
        "# batched count log2_ops leaf tile workgroups_per_cu\n";
   for (auto& [key, val] : g_tune)
     f << "leaf " << key.semiring << ' ' << key.m << ' ' << key.k << ' ' << key.n << ' '
@@ -916,7 +1025,7 @@ int bmm_autotune_save(const char* path) {
       << val.tile[3] << '\n';
   for (auto& [key, val] : g_depth)
     f << "depth " << std::get<0>(key) << ' ' << std::get<1>(key) << ' ' << std::get<2>(key)
-      << ' ' << val.first << ' ' << val.second << '\n';
+      << ' ' << std::get<0>(val) << ' ' << std::get<1>(val) << ' ' << std::get<2>(val) << '\n';
   for (auto& [key, val] : g_batched)
     f << "batched " << key.first << ' ' << key.second << ' ' << std::get<0>(val) << ' '
       << std::get<1>(val) << ' ' << std::get<2>(val) << '\n';
@@ -946,9 +1055,12 @@ int bmm_autotune_load(const char* path) {
       v.tile[2] = t2;
       v.tile[3] = t3;
     } else if (sscanf(line.c_str(), "depth %lld %lld %lld %d %d", &m, &k, &n, &d, &ds) == 5) {
-      if (d < 0 || ds < 0 || ds > d) return fail(BMM_E_INVAL, "bad depth line: %s", line.c_str());
+      int sh = 0;  // lines without the shift column: the plain leaf
+      if (sscanf(line.c_str(), "depth %lld %lld %lld %d %d %d", &m, &k, &n, &d, &ds, &sh) < 5 ||
+          d < 0 || ds < 0 || ds > d || sh < 0 || sh > 2)
+        return fail(BMM_E_INVAL, "bad depth line: %s", line.c_str());
       std::lock_guard<std::mutex> lock(g_mu);
-      g_depth[{m, k, n}] = {d, ds};
+      g_depth[{m, k, n}] = {d, ds, sh};
     } else if (sscanf(line.c_str(), "batched %lld %d %d %d %d", &m, &d, &leaf, &t1, &t2) >= 4) {
       if (sscanf(line.c_str(), "batched %lld %d %d %d %d", &m, &d, &leaf, &t1, &t2) == 4) t2 = 4;
       if (m <= 0 || d < 0 || (leaf != BMM_LEAF_MFMA_I8 && leaf != BMM_LEAF_MFMA_F4) ||
@@ -956,6 +1068,7 @@ int bmm_autotune_load(const char* path) {
         return fail(BMM_E_INVAL, "bad batched line: %s", line.c_str());
       std::lock_guard<std::mutex> lock(g_mu);
       g_batched[{m, d}] = {leaf, t1, t2};
+      ++g_batched_gen;
     } else {
       return fail(BMM_E_INVAL, "bad line in %s: %s", path, line.c_str());
     }
@@ -980,6 +1093,7 @@ const char* bmm_last_error(void) { return g_last_error.c_str(); }
 const char* bmm_version(void) { return "bmm 0.1 (gfx950)"; }
 
 void bmm_finalize(void) {
+  batched_cache_clear();
   std::lock_guard<std::mutex> lock(g_mu);
   if (!g_scratch.empty()) (void)hipDeviceSynchronize();
   int cur = 0;
@@ -995,6 +1109,7 @@ void bmm_finalize(void) {
   g_tune.clear();
   g_depth.clear();
   g_batched.clear();
+  ++g_batched_gen;
 }
 
 }  // extern "C"

@@ -5,6 +5,8 @@
 #include <algorithm>
 #include <cstdarg>
 #include <cstdio>
+#include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -27,7 +29,57 @@ struct Plan {
   int device = 0;
   int leaf = BMM_LEAF_MFMA_I8;  // BMM_LEAF_MFMA_I8 or BMM_LEAF_MFMA_F4
   int tile = 2;                 // 1: 128 x 64 per wave, 2: 64 x 64, 3: 64 x 128
+  // Marks the end of the last launch enqueued outside stream capture; the next launch
+  // (on any stream) waits for it, so launches that share the queue counters never overlap.
+  hipEvent_t done = nullptr;
 };
+
+bool capturing(hipStream_t s) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  return hipStreamIsCapturing(s, &st) == hipSuccess && st != hipStreamCaptureStatusNone;
+}
+
+// Launch a plan's kernels (counter reset + persistent kernel) on s.  Outside stream
+// capture the launch is ordered after the plan's previous one by its event.
+int plan_enqueue(Plan* P, hipStream_t s) {
+  if (P->count == 0) return BMM_OK;
+  const bool cap = capturing(s);
+  if (!cap) {
+    if (!P->done && hipEventCreateWithFlags(&P->done, hipEventDisableTiming) != hipSuccess)
+      return bfail(BMM_E_DEVICE, "plan event: %s", hipGetErrorString(hipGetLastError()));
+    if (hipStreamWaitEvent(s, P->done, 0) != hipSuccess)
+      return bfail(BMM_E_DEVICE, "plan order: %s", hipGetErrorString(hipGetLastError()));
+  }
+  hipError_t e = launch_batched_persistent(
+      P->descs, P->segs, P->queues, P->counters, P->grid, P->tile,
+      P->leaf == BMM_LEAF_MFMA_F4 ? 1 : 0, s);
+  if (e != hipSuccess) return bfail(BMM_E_DEVICE, "batched launch: %s", hipGetErrorString(e));
+  if (!cap && hipEventRecord(P->done, s) != hipSuccess)
+    return bfail(BMM_E_DEVICE, "plan event: %s", hipGetErrorString(hipGetLastError()));
+  return BMM_OK;
+}
+
+void plan_free(Plan* P) {
+  if (P->descs || P->counters || P->done) {
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(P->device);
+    if (P->done) {
+      (void)hipEventSynchronize(P->done);
+      (void)hipEventDestroy(P->done);
+    } else {
+      (void)hipDeviceSynchronize();
+    }
+    (void)hipFree(P->descs);
+    (void)hipFree(P->segs);
+    (void)hipFree(P->counters);
+    (void)hipSetDevice(cur);
+  }
+  P->descs = nullptr;
+  P->segs = nullptr;
+  P->counters = nullptr;
+  P->done = nullptr;
+}
 
 int validate_problem(const bmm_problem& p, int64_t i) {
   if (p.semiring != BMM_GF2 && p.semiring != BMM_BOOLEAN)
@@ -176,6 +228,146 @@ int build_plan(const bmm_problem* problems, int64_t count, const bmm_options* op
   return BMM_OK;
 }
 
+#define BMM_BTRY(expr)              \
+  do {                              \
+    int _rc = (expr);               \
+    if (_rc != BMM_OK) return _rc;  \
+  } while (0)
+
+// Library-owned plans of bmm_batched, keyed by the problem table (pointers, sizes,
+// pitches, semirings), the leaf and tile options and the device.  An entry owns the
+// device problem table, a staging buffer for right operands not given transposed,
+// and a HIP graph of its launch sequence (the transposes into staging, the counter
+// reset and the persistent kernel), captured on its first call and replayed on the
+// caller's stream by later calls.  Launches of one entry are ordered by its event.
+struct BatchedEntry {
+  std::vector<bmm_problem> key;
+  int leaf = 0, tile = 0, device = 0;
+  uint64_t tune_gen = 0;  // the batched tuning records the plan was built from
+  Plan plan;
+  std::vector<bmm_problem> staged;  // the problems as the plan sees them (B^T everywhere)
+  uint64_t* stage = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t done = nullptr;
+  uint64_t used = 0;
+
+  static bool same(const bmm_problem& a, const bmm_problem& b) {
+    return a.semiring == b.semiring && a.m == b.m && a.k == b.k && a.n == b.n && a.A == b.A &&
+           a.B == b.B && a.C == b.C && a.lda == b.lda && a.ldb == b.ldb && a.ldc == b.ldc &&
+           (a.b_transposed != 0) == (b.b_transposed != 0);
+  }
+  bool matches(const bmm_problem* p, int64_t count, int lf, int tl, int dev) const {
+    if (dev != device || lf != leaf || tl != tile || (int64_t)key.size() != count ||
+        tune_gen != batched_tune_generation())
+      return false;
+    for (int64_t i = 0; i < count; ++i)
+      if (!same(key[(size_t)i], p[i])) return false;
+    return true;
+  }
+
+  // The transposes of untransposed right operands, then the plan's kernels.
+  int enqueue(hipStream_t s) {
+    for (size_t i = 0; i < key.size(); ++i) {
+      const bmm_problem& p = key[i];
+      if (p.b_transposed || p.m == 0 || p.n == 0 || p.k == 0) continue;
+      const bmm_problem& q = staged[i];
+      hipError_t e = launch_transpose(p.B, p.ldb, 0, const_cast<uint64_t*>(q.B), q.ldb, 0, p.k,
+                                      p.n, 1, s);
+      if (e != hipSuccess) return bfail(BMM_E_DEVICE, "transpose: %s", hipGetErrorString(e));
+    }
+    if (plan.count == 0) return BMM_OK;
+    hipError_t e = launch_batched_persistent(plan.descs, plan.segs, plan.queues, plan.counters,
+                                             plan.grid, plan.tile,
+                                             plan.leaf == BMM_LEAF_MFMA_F4 ? 1 : 0, s);
+    if (e != hipSuccess) return bfail(BMM_E_DEVICE, "batched launch: %s", hipGetErrorString(e));
+    return BMM_OK;
+  }
+
+  int build(const bmm_problem* p, int64_t count, const bmm_options* opt, int lf, int tl,
+            int dev) {
+    key.assign(p, p + count);
+    tune_gen = batched_tune_generation();
+    leaf = lf;
+    tile = tl;
+    device = dev;
+    staged = key;
+    size_t need = 0;
+    for (const auto& q : key)
+      if (!q.b_transposed && q.m > 0 && q.n > 0 && q.k > 0)
+        need += (size_t)q.n * ((q.k + 63) / 64) * 8;
+    if (need && hipMalloc((void**)&stage, need) != hipSuccess) {
+      (void)hipGetLastError();
+      stage = nullptr;
+      return bfail(BMM_E_NOMEM, "batched staging of %zu bytes", need);
+    }
+    size_t off = 0;
+    for (auto& q : staged) {
+      if (!q.b_transposed && q.m > 0 && q.n > 0 && q.k > 0) {
+        const int64_t kw = (q.k + 63) / 64;
+        q.B = stage + off / 8;
+        q.ldb = kw;
+        off += (size_t)q.n * kw * 8;
+      }
+      q.b_transposed = 1;
+    }
+    BMM_BTRY(build_plan(staged.data(), count, opt, 0, &plan));
+    if (hipEventCreateWithFlags(&done, hipEventDisableTiming) != hipSuccess)
+      return bfail(BMM_E_DEVICE, "batched event: %s", hipGetErrorString(hipGetLastError()));
+    // capture the sequence once; if this runtime cannot, launches enqueue it directly
+    hipStream_t cs = nullptr;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) == hipSuccess) {
+      bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+      const int rc = ok ? enqueue(cs) : BMM_OK;
+      hipGraph_t g = nullptr;
+      if (ok) ok = hipStreamEndCapture(cs, &g) == hipSuccess && rc == BMM_OK && g;
+      if (ok && hipGraphInstantiate(&exec, g, nullptr, nullptr, 0) == hipSuccess) {
+        graph = g;
+      } else {
+        exec = nullptr;
+        if (g) (void)hipGraphDestroy(g);
+      }
+      (void)hipGetLastError();
+      (void)hipStreamDestroy(cs);
+    }
+    return BMM_OK;
+  }
+
+  int launch(hipStream_t s, bool cap) {
+    if (cap) return enqueue(s);  // inside the caller's capture: the kernels themselves
+    if (hipStreamWaitEvent(s, done, 0) != hipSuccess)
+      return bfail(BMM_E_DEVICE, "batched order: %s", hipGetErrorString(hipGetLastError()));
+    if (exec) {
+      if (hipGraphLaunch(exec, s) != hipSuccess)
+        return bfail(BMM_E_DEVICE, "batched graph launch: %s",
+                     hipGetErrorString(hipGetLastError()));
+    } else {
+      BMM_BTRY(enqueue(s));
+    }
+    if (hipEventRecord(done, s) != hipSuccess)
+      return bfail(BMM_E_DEVICE, "batched event: %s", hipGetErrorString(hipGetLastError()));
+    return BMM_OK;
+  }
+
+  ~BatchedEntry() {
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(device);
+    if (done) (void)hipEventSynchronize(done);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (done) (void)hipEventDestroy(done);
+    plan_free(&plan);
+    (void)hipFree(stage);
+    (void)hipSetDevice(cur);
+  }
+};
+
+constexpr size_t kBatchedCacheEntries = 8;
+std::mutex g_batched_mu;
+std::vector<std::unique_ptr<BatchedEntry>> g_entries;
+uint64_t g_batched_clock = 0;
+
 }  // namespace
 
 extern "C" {
@@ -195,28 +387,13 @@ int bmm_batched_plan_create(const bmm_problem* problems, int64_t count,
 
 int bmm_batched_plan_launch(void* plan, void* hip_stream) {
   if (!plan) return bfail(BMM_E_INVAL, "null plan");
-  Plan* P = static_cast<Plan*>(plan);
-  if (P->count == 0) return BMM_OK;
-  hipError_t e = launch_batched_persistent(
-      P->descs, P->segs, P->queues, P->counters, P->grid, P->tile,
-      P->leaf == BMM_LEAF_MFMA_F4 ? 1 : 0, (hipStream_t)hip_stream);
-  if (e != hipSuccess) return bfail(BMM_E_DEVICE, "batched launch: %s", hipGetErrorString(e));
-  return BMM_OK;
+  return plan_enqueue(static_cast<Plan*>(plan), (hipStream_t)hip_stream);
 }
 
 void bmm_batched_plan_destroy(void* plan) {
   if (!plan) return;
   Plan* P = static_cast<Plan*>(plan);
-  if (P->descs || P->counters) {
-    int cur = 0;
-    (void)hipGetDevice(&cur);
-    (void)hipSetDevice(P->device);
-    (void)hipDeviceSynchronize();
-    (void)hipFree(P->descs);
-    (void)hipFree(P->segs);
-    (void)hipFree(P->counters);
-    (void)hipSetDevice(cur);
-  }
+  plan_free(P);
   delete P;
 }
 
@@ -285,56 +462,47 @@ int bmm_batched(const bmm_problem* problems, int64_t count, const bmm_options* o
                 void* hip_stream) {
   if (count < 0 || (count > 0 && !problems)) return bfail(BMM_E_INVAL, "bad problem list");
   if (count == 0) return BMM_OK;
-  hipStream_t s = (hipStream_t)hip_stream;
-  // Stage non-transposed right operands into one scratch allocation.
-  std::vector<bmm_problem> probs(problems, problems + count);
-  size_t need = 0;
   for (int64_t i = 0; i < count; ++i) {
-    int rc = validate_problem(probs[i], i);
+    int rc = validate_problem(problems[i], i);
     if (rc != BMM_OK) return rc;
-    if (!probs[i].b_transposed && probs[i].m > 0 && probs[i].n > 0 && probs[i].k > 0)
-      need += (size_t)probs[i].n * ((probs[i].k + 63) / 64) * 8;
   }
-  uint64_t* stage = nullptr;
-  if (need) {
-    if (hipMalloc((void**)&stage, need) != hipSuccess) {
-      (void)hipGetLastError();
-      return bfail(BMM_E_NOMEM, "batched staging of %zu bytes", need);
+  hipStream_t s = (hipStream_t)hip_stream;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return bfail(BMM_E_DEVICE, "hipGetDevice");
+  const int leaf = opt ? opt->leaf : BMM_LEAF_AUTO, tile = opt ? opt->tile : 0;
+  std::lock_guard<std::mutex> lock(g_batched_mu);
+  BatchedEntry* E = nullptr;
+  const uint64_t gen = batched_tune_generation();
+  g_entries.erase(std::remove_if(g_entries.begin(), g_entries.end(),
+                                 [gen](const auto& e) { return e->tune_gen != gen; }),
+                  g_entries.end());
+  for (auto& e : g_entries)
+    if (e->matches(problems, count, leaf, tile, dev)) E = e.get();
+  const bool cap = capturing(s);
+  if (!E) {
+    if (cap)
+      return bfail(BMM_E_UNSUPPORTED, "the first bmm_batched call with a problem table "
+                   "builds its plan (allocation, upload) and must run outside stream capture");
+    auto fresh = std::make_unique<BatchedEntry>();
+    BMM_BTRY(fresh->build(problems, count, opt, leaf, tile, dev));
+    if (g_entries.size() >= kBatchedCacheEntries) {
+      // least recently used first
+      auto lru = std::min_element(g_entries.begin(), g_entries.end(),
+                                  [](const auto& a, const auto& b) { return a->used < b->used; });
+      g_entries.erase(lru);
     }
-    size_t off = 0;
-    for (int64_t i = 0; i < count; ++i) {
-      bmm_problem& p = probs[i];
-      if (p.b_transposed || p.m == 0 || p.n == 0 || p.k == 0) {
-        p.b_transposed = 1;
-        if (p.k == 0) p.ldb = std::max<int64_t>(p.ldb, 0);
-        continue;
-      }
-      const int64_t kw = (p.k + 63) / 64;
-      uint64_t* bt = stage + off / 8;
-      hipError_t e = launch_transpose(p.B, p.ldb, 0, bt, kw, 0, p.k, p.n, 1, s);
-      if (e != hipSuccess) {
-        (void)hipFree(stage);
-        return bfail(BMM_E_DEVICE, "transpose: %s", hipGetErrorString(e));
-      }
-      p.B = bt;
-      p.ldb = kw;
-      p.b_transposed = 1;
-      off += (size_t)p.n * kw * 8;
-    }
-  } else {
-    for (auto& p : probs) p.b_transposed = 1;
+    g_entries.push_back(std::move(fresh));
+    E = g_entries.back().get();
   }
-  void* plan = nullptr;
-  int rc = bmm_batched_plan_create(probs.data(), count, opt, &plan);
-  if (rc == BMM_OK) rc = bmm_batched_plan_launch(plan, hip_stream);
-  if (rc == BMM_OK && hipStreamSynchronize(s) != hipSuccess)
-    rc = bfail(BMM_E_DEVICE, "batched sync: %s", hipGetErrorString(hipGetLastError()));
-  bmm_batched_plan_destroy(plan);
-  if (stage) {
-    (void)hipStreamSynchronize(s);
-    (void)hipFree(stage);
-  }
-  return rc;
+  E->used = ++g_batched_clock;
+  return E->launch(s, cap);
 }
 
 }  // extern "C"
+
+namespace bmm {
+void batched_cache_clear() {
+  std::lock_guard<std::mutex> lock(g_batched_mu);
+  g_entries.clear();
+}
+}  // namespace bmm

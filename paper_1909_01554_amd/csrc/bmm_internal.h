@@ -87,6 +87,28 @@ hipError_t launch_leaf_mfma_f4(int semiring, const LeafBatch& p, int tile, hipSt
 // The 8-wave workgroup variant that shares operand panels through LDS (fmt 0: int8, 1: fp4).
 hipError_t launch_leaf_mfma_lds(int semiring, int fmt, const LeafBatch& p, hipStream_t s);
 hipError_t launch_leaf_valu(int semiring, const LeafBatch& p, int tile, hipStream_t s);
+// The last recursion level shifted into the int8 leaf (leaf_shift.hip): for every
+// parent p, the seven child products of its quadrants (alpha, beta of `scheme`) are
+// formed, multiplied and combined by gamma into the parent's result quadrants.
+// m, k, n: a CHILD product's sizes (parents are 2m x 2k and 2n x 2k transposed,
+// results 2m x 2n); parent p at base + p * stride (words).  accumulate: Q ^= result.
+struct ShiftBatch {
+  const uint64_t* T;
+  int64_t ldt, strideT;
+  const uint64_t* S;
+  int64_t lds, strideS;
+  uint64_t* Q;
+  int64_t ldq, strideQ;
+  int64_t m, k, n, parents;
+  int accumulate;
+};
+// Schemes with alpha/beta weights <= 2 (self-inverse, chaining), k = 2048 or 4096
+// bits, n a multiple of 64.
+bool leaf_shift_supported(int scheme, int64_t m, int64_t k, int64_t n);
+// The kernel addresses a parent's rows with 32-bit byte offsets (2 * rows * ld < 2^29).
+bool leaf_shift_fits(int64_t rows, int64_t ld);
+// kv = 2: 16-byte operand loads where operands and pitches allow, else 8-byte loads.
+hipError_t launch_leaf_shift(int scheme, const ShiftBatch& p, int kv, hipStream_t s);
 int leaf_mfma_tile_rows(int tile);
 int leaf_mfma_tile_cols(int tile);
 
@@ -176,6 +198,10 @@ constexpr int kBatchedCounterStride = 64;  // uint32s between queue counters (25
 hipError_t launch_batched_persistent(const BatchedDesc* descs, const BatchedSeg* segs,
                                      const BatchedQueues& queues, unsigned int* counters,
                                      int grid, int tile, int fmt, hipStream_t s);
+// Generation of the batched tuning records (changes whenever one is set or loaded).
+uint64_t batched_tune_generation();
+// Release bmm_batched's library-owned plans, graphs and staging buffers.
+void batched_cache_clear();
 int batched_tile_rows(int tile);
 int batched_tile_cols(int tile);
 

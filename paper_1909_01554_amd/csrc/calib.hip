@@ -121,25 +121,25 @@ extern "C" int bmm_calibrate_valu(int waves_per_simd, int64_t rounds, double* la
   (void)hipFree(sink);
   (void)hipFree(stamps);
   if (rc != BMM_OK) return rc;
-  // per wave: bitop3 instructions per core cycle and core cycles per second
+  // core clock: per wave, core cycles over constant-rate time; the median over waves
   const double insts = (double)rounds * calib_chains();
-  std::vector<double> rate, clk;
+  std::vector<double> clk;
   for (int w = 0; w < waves; ++w) {
     const double cyc = (double)(st[4 * w + 1] - st[4 * w]);
     const double sec = (double)(st[4 * w + 3] - st[4 * w + 2]) / (wall_khz * 1e3);
-    if (cyc <= 0 || sec <= 0) continue;
-    rate.push_back(insts / cyc);
-    clk.push_back(cyc / sec);
+    if (cyc > 0 && sec > 0) clk.push_back(cyc / sec);
   }
-  if (rate.empty()) return set_error(BMM_E_DEVICE, "calibration: no valid wave timings");
-  std::sort(rate.begin(), rate.end());
+  if (clk.empty() || ms <= 0.f) return set_error(BMM_E_DEVICE, "calibration: no valid timings");
   std::sort(clk.begin(), clk.end());
-  const double r_med = rate[rate.size() / 2], c_med = clk[clk.size() / 2];
-  // waves_per_simd waves share a SIMD; 64 lanes per instruction, 4 SIMDs per CU
-  if (lane_ops_per_clk_cu) *lane_ops_per_clk_cu = r_med * waves_per_simd * 64.0 * 4.0;
+  const double c_med = clk[clk.size() / 2];
+  const double sec = ms * 1e-3;
+  // the whole launch: every wave's instructions over the launch's core cycles (waves
+  // need not all be resident at once, so per-wave rates would overstate a SIMD's)
+  const double lane_ops = insts * waves * 64.0;
+  if (lane_ops_per_clk_cu) *lane_ops_per_clk_cu = lane_ops / (sec * c_med * cus);
   if (clock_ghz) *clock_ghz = c_med * 1e-9;
-  if (seconds) *seconds = ms * 1e-3;
-  // the whole launch: 2 bit operations on each of 32 bit positions per lane operation
-  if (aggregate_bops) *aggregate_bops = insts * waves * 64.0 * 64.0 / (ms * 1e-3);
+  if (seconds) *seconds = sec;
+  // 2 bit operations on each of 32 bit positions per lane operation
+  if (aggregate_bops) *aggregate_bops = lane_ops * 64.0 / sec;
   return BMM_OK;
 }

@@ -43,7 +43,7 @@ def test_autotuned_strassen_depth_is_exact(bmm, tmp_path):
                  for d in range(0, 3))
     ws = torch.empty(nbytes // 8 + 1, dtype=torch.int64, device="cuda")
     announce("autotune strassen")
-    d, ds, secs = bmm.bmm_autotune_strassen(Ad, Bd, Cd, n, n, n, ws)
+    d, ds, shift, secs = bmm.bmm_autotune_strassen(Ad, Bd, Cd, n, n, n, ws)
     assert 0 <= ds <= d <= 2 and secs > 0
     Cd.fill_(-1)
     bmm.bmm_gf2_strassen(Ad, Bd, Cd, n, n, n, ws, depth=-1)

@@ -218,3 +218,103 @@ def test_ooc_rejects_pageable(bmm):
     with pytest.raises(bmm.BmmError) as e:
         bmm.bmm_ooc(0, A, A.copy(), A.copy(), 64, 64, 64)
     assert e.value.status == -1
+
+
+def test_batched_cached_plan_replays(bmm):
+    """bmm_batched keeps a plan (and its graph) per problem table: a second call on
+    the same buffers with new contents replays it and reads the new operands; calls
+    on two streams with the same table are ordered by the library; inside a stream
+    capture the call records its kernels into the caller's graph."""
+    import torch
+    probs, host = make_problems(20, 303, transposed=False)
+    announce("batched cache first call")
+    bmm.bmm_batched(probs)
+    check(probs, host)
+    # new operand contents in the same buffers: the cached table points at them
+    host2 = []
+    for p, (pr, (sr, A, B, m, k, n)) in enumerate(zip(probs, host)):
+        dist = bmmgen.Dist.half() if sr == oracle.GF2 else bmmgen.Dist.inv_sqrt(max(k, 1))
+        A2 = bmmgen.fill_cpu(m, max(k, 1), 404, bmmgen.batched_tag(p, "A"), dist)
+        if k == 0:
+            A2[:] = 0
+        pr["A"].copy_(to_dev(A2))
+        pr["C"].fill_(-1)
+        host2.append((sr, A2, B, m, k, n))
+    torch.cuda.synchronize()
+    announce("batched cache replay, new contents")
+    bmm.bmm_batched(probs)
+    check(probs, host2)
+    # two streams back to back with no host synchronization in between
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    for pr in probs:
+        pr["C"].fill_(-1)
+    torch.cuda.synchronize()
+    announce("batched cache, two streams")
+    bmm.bmm_batched(probs, stream=s1.cuda_stream)
+    bmm.bmm_batched(probs, stream=s2.cuda_stream)
+    torch.cuda.synchronize()
+    check(probs, host2)
+    # captured into a torch graph (the plan exists already), replayed three times
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s1):
+        bmm.bmm_batched(probs, stream=s1.cuda_stream)
+    for rep in range(3):
+        for pr in probs:
+            pr["C"].fill_(-1)
+        torch.cuda.synchronize()
+        announce("batched cache captured replay", rep)
+        g.replay()
+        torch.cuda.synchronize()
+        check(probs, host2)
+
+
+def test_batched_cache_eviction_and_capture_refusal(bmm):
+    import torch
+    tables = [make_problems(3, 600 + i, maxdim=200) for i in range(10)]
+    for i, (probs, host) in enumerate(tables):  # more tables than the cache holds
+        announce("batched cache table", i)
+        bmm.bmm_batched(probs)
+        check(probs, host)
+    probs, host = tables[0]  # evicted by now: rebuilt on this call
+    for pr in probs:
+        pr["C"].fill_(-1)
+    announce("batched cache rebuilt table")
+    bmm.bmm_batched(probs)
+    check(probs, host)
+    fresh, _ = make_problems(3, 700, maxdim=200)
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    announce("batched first call inside capture")
+    with torch.cuda.graph(g, stream=s):
+        with pytest.raises(bmm.BmmError) as e:
+            bmm.bmm_batched(fresh, stream=s.cuda_stream)
+        fresh[0]["C"].fill_(0)  # keep the captured graph non-empty
+    assert e.value.status == -2
+
+
+@pytest.mark.parametrize("which", ["gf2", "boolean", "strassen"])
+def test_host_operands_through_product_calls(bmm, which):
+    """BMM_FLAG_HOST_OPERANDS on bmm_gf2, bmm_boolean and bmm_gf2_strassen runs the
+    out-of-core pipeline on page-locked host tensors (cubic block order for the
+    cubic calls, host-level recursion levels for the Strassen call)."""
+    import torch
+    m = k = n = 2048 if which == "strassen" else 1000
+    sr = oracle.BOOLEAN if which == "boolean" else oracle.GF2
+    dist = bmmgen.Dist.half() if sr == oracle.GF2 else bmmgen.Dist.pow2(5)
+    A = bmmgen.fill_cpu(m, k, 44, bmmgen.TAG_A, dist)
+    B = bmmgen.fill_cpu(k, n, 44, bmmgen.TAG_B, dist)
+    Ah = torch.from_numpy(A.view(np.int64)).pin_memory()
+    Bh = torch.from_numpy(B.view(np.int64)).pin_memory()
+    Ch = torch.full((m, words(n)), -1, dtype=torch.int64).pin_memory()
+    opts = bmm.Options(block=1024 if which == "strassen" else 384)
+    announce("host operands", which)
+    if which == "strassen":
+        bmm.bmm_gf2_strassen(Ah, Bh, Ch, m, k, n, None, options=opts, host_operands=True)
+    else:
+        fn = bmm.bmm_gf2 if sr == oracle.GF2 else bmm.bmm_boolean
+        fn(Ah, Bh, Ch, m, k, n, options=opts, host_operands=True)
+    assert np.array_equal(Ch.numpy().view(np.uint64), oracle.mul(A, B, k, n, sr))
+    with pytest.raises(bmm.BmmError) as e:  # no accumulation out of core
+        bmm.bmm_gf2(Ah, Bh, Ch, m, k, n, accumulate=True, host_operands=True)
+    assert e.value.status == -2

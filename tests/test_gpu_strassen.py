@@ -179,6 +179,80 @@ def test_strassen_product(bmm, m, k, n, depth, ds, leaf):
     assert np.array_equal(from_dev(Ad), A) and np.array_equal(from_dev(Bd), B)
 
 
+SHIFT_CASES = [  # m, k, n, depth, depth_serial: leaves of k = 2048 or 4096 bits
+    (4096, 4096, 4096, 1, 0),     # the parent is the whole (staged) operand, Q is C
+    (8192, 8192, 8192, 2, 0),     # one expanded level above the shifted one
+    (8192, 8192, 8192, 2, 1),     # parents are the serial level's children
+    (4000, 4096, 2048, 1, 0),     # child rows 2000: a ragged last row tile
+    (4096, 8192, 2048, 1, 0),     # leaves of k = 4096
+    (8192, 16384, 4096, 3, 1),    # rectangular, serial + merged parallel levels
+]
+
+
+@pytest.mark.parametrize("m,k,n,depth,ds", SHIFT_CASES)
+@pytest.mark.parametrize("shift", [1, 2])
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_strassen_shifted_leaf(bmm, m, k, n, depth, ds, shift, scheme):
+    """The last parallel level inside the int8 leaf (section 3.15): every parent's
+    seven products formed from its quadrants in registers and combined in LDS reach
+    AB exactly, with 16-byte (shift 1) and 8-byte (shift 2) operand loads."""
+    import torch
+    seed = 300 + m + k + depth + 7 * shift + scheme
+    A = bmmgen.fill_cpu(m, k, seed, bmmgen.TAG_A, bmmgen.Dist.half())
+    B = bmmgen.fill_cpu(k, n, seed, bmmgen.TAG_B, bmmgen.Dist.half())
+    opts = bmm.Options(leaf=2, depth_serial=ds, depth_parallel=depth - ds, scheme=scheme,
+                       shift=shift)
+    plain = bmm.Options(leaf=2, depth_serial=ds, depth_parallel=depth - ds, scheme=scheme,
+                        shift=0)
+    nbytes, _, _ = bmm.bmm_gf2_strassen_workspace(m, k, n, depth, opts)
+    assert nbytes < bmm.bmm_gf2_strassen_workspace(m, k, n, depth, plain)[0]
+    ws = torch.empty(nbytes // 8 + 1, dtype=torch.int64, device="cuda")
+    Cd = empty_dev(m, words(n) + 1, fill=-1)
+    announce("strassen shifted leaf", m, k, n, depth, ds, shift, scheme)
+    bmm.bmm_gf2_strassen(to_dev(A), to_dev(B), Cd, m, k, n, ws, depth=depth, options=opts)
+    got = from_dev(Cd, words(n))
+    if m * k * n <= 8192 ** 3:
+        assert np.array_equal(got, oracle.mul(A, B, k, n, oracle.GF2))
+    else:
+        rows = bmmgen.stratified_rows(m, 256, seed)
+        assert np.array_equal(got[rows], oracle.rows(A[rows], B, k, n, oracle.GF2))
+        X = bmmgen.freivalds_vectors(m, 4, seed)
+        assert all(oracle.freivalds(A, B, got, m, k, n, X))
+
+
+@pytest.mark.parametrize("scheme", [0, 1, 2])
+@pytest.mark.parametrize("alt", [False, True])
+def test_strassen_shifted_leaf_accumulate_inplace(bmm, scheme, alt):
+    """The shifted leaf accumulating into C (standard and alternative basis), on
+    operands changed in place with odd pitches (8-byte loads).  Winograd has no
+    shifted leaf: the option falls back to the plain one."""
+    import torch
+    from oracle import brute
+    m, k, n, d = 4096, 8192, 4096, 1  # one level: the parent is the caller's operand
+    seed = 41 + scheme + (9 if alt else 0)
+    A = bmmgen.fill_cpu(m, k, seed, bmmgen.TAG_A, bmmgen.Dist.half())
+    B = bmmgen.fill_cpu(k, n, seed, bmmgen.TAG_B, bmmgen.Dist.half())
+    C0 = bmmgen.fill_cpu(m, n, seed, 0xC, bmmgen.Dist.half())
+    dec = DECS[scheme]
+    if alt:
+        A = strassen.basis(A, d, dec.fwd)
+        B = strassen.basis(B, d, dec.fwd)
+        prod = strassen.core(A, B, d, strassen.packed_leaf(k >> d, n >> d), dec)
+    else:
+        prod = oracle.mul(A, B, k, n, oracle.GF2)
+    BT = brute.pack(brute.unpack(B, n).T.copy())
+    opts = bmm.Options(leaf=2, depth_serial=0, depth_parallel=d, scheme=scheme, shift=1)
+    kw = dict(b_transposed=True, alt_basis_io=alt, inplace_basis=not alt)
+    nbytes, _, _ = bmm.bmm_gf2_strassen_workspace(m, k, n, d, opts, **kw)
+    ws = torch.empty(nbytes // 8 + 1, dtype=torch.int64, device="cuda")
+    Ad, Bd, Cd = to_dev(A, words(k) + 1), to_dev(BT, words(k) + 1), to_dev(C0)
+    announce("strassen shifted accumulate", scheme, alt)
+    bmm.bmm_gf2_strassen(Ad, Bd, Cd, m, k, n, ws, depth=d, options=opts, accumulate=True, **kw)
+    assert np.array_equal(from_dev(Cd), C0 ^ prod)
+    assert np.array_equal(from_dev(Ad, words(k)), A)
+    assert np.array_equal(from_dev(Bd, words(k)), BT)
+
+
 @pytest.mark.parametrize("leaf", [2, 3])
 @pytest.mark.parametrize("m,k,n,depth", [(8192, 8192, 8192, 2), (8192, 8192, 4096, 1),
                                          (8192, 4096, 2048, 1)])
@@ -305,6 +379,70 @@ def test_strassen_accumulate(bmm, alt, depth, ds, scheme):
     assert np.array_equal(from_dev(Cd, words(n)), C0 ^ prod)
 
 
+@pytest.mark.parametrize("scheme", [0, 1, 2])
+@pytest.mark.parametrize("b_t", [False, True])
+@pytest.mark.parametrize("depth,ds,accumulate", [(1, 0, False), (3, 1, True), (4, 2, False),
+                                                 (2, 2, True)])
+def test_strassen_inplace_basis(bmm, scheme, b_t, depth, ds, accumulate):
+    """BMM_FLAG_INPLACE_BASIS: A (and B^T when passed transposed) change basis in
+    place; C is AB (or C ^ AB) and both operands hold their original words again
+    afterwards (the changes are invertible in place, sections 2.2, 2.3, 3.6).  The
+    workspace shrinks by the operands that are no longer copied."""
+    import torch
+    from oracle import brute
+    m, k, n = 512 << (depth // 2), 1024, 2048 if depth == 4 else 1536
+    seed = 500 + 10 * depth + scheme + (5 if b_t else 0)
+    A = bmmgen.fill_cpu(m, k, seed, bmmgen.TAG_A, bmmgen.Dist.half())
+    B = bmmgen.fill_cpu(k, n, seed, bmmgen.TAG_B, bmmgen.Dist.half())
+    C0 = bmmgen.fill_cpu(m, n, seed, 0xC, bmmgen.Dist.half())
+    Bin = brute.pack(brute.unpack(B, n).T.copy()) if b_t else B
+    opts = bmm.Options(leaf=2, depth_serial=ds, depth_parallel=depth - ds, scheme=scheme)
+    full, _, _ = bmm.bmm_gf2_strassen_workspace(m, k, n, depth, opts, b_transposed=b_t)
+    nbytes, _, _ = bmm.bmm_gf2_strassen_workspace(m, k, n, depth, opts, b_transposed=b_t,
+                                                  inplace_basis=True)
+    saved = m * words(k) * 8 + (n * words(k) * 8 if b_t else 0)
+    assert full - nbytes == saved
+    ws = torch.empty(nbytes // 8 + 1, dtype=torch.int64, device="cuda")
+    Ad = to_dev(A, words(k) + 1)
+    Bd = to_dev(Bin, Bin.shape[1] + 2)
+    Cd = to_dev(C0) if accumulate else empty_dev(m, words(n), fill=-1)
+    announce("strassen inplace", scheme, b_t, depth, ds, accumulate)
+    bmm.bmm_gf2_strassen(Ad, Bd, Cd, m, k, n, ws, depth=depth, options=opts, b_transposed=b_t,
+                         accumulate=accumulate, inplace_basis=True)
+    prod = oracle.mul(A, B, k, n, oracle.GF2)
+    assert np.array_equal(from_dev(Cd), (C0 ^ prod) if accumulate else prod)
+    assert np.array_equal(from_dev(Ad, words(k)), A)
+    assert np.array_equal(from_dev(Bd, Bin.shape[1]), Bin)
+
+
+def test_strassen_alt_io_transposed_b_in_place(bmm):
+    """Alternative-basis input with B passed transposed is read where it lies (no
+    copy in the workspace) and left unchanged."""
+    import torch
+    from oracle import brute
+    m = k = n = 1024
+    d = 2
+    A = bmmgen.fill_cpu(m, k, 8, bmmgen.TAG_A, bmmgen.Dist.half())
+    B = bmmgen.fill_cpu(k, n, 8, bmmgen.TAG_B, bmmgen.Dist.half())
+    Ah = strassen.basis(A, d, algebra.sinv_fwd)
+    Bh = strassen.basis(B, d, algebra.sinv_fwd)
+    want_hat = strassen.core(Ah, Bh, d, strassen.packed_leaf(k >> d, n >> d))
+    BhT = brute.pack(brute.unpack(Bh, n).T.copy())
+    opts = bmm.Options(leaf=2)
+    with_copy, _, _ = bmm.bmm_gf2_strassen_workspace(m, k, n, d, opts, alt_basis_io=True)
+    nbytes, _, _ = bmm.bmm_gf2_strassen_workspace(m, k, n, d, opts, alt_basis_io=True,
+                                                  b_transposed=True)
+    assert with_copy - nbytes == n * words(k) * 8
+    ws = torch.empty(nbytes // 8 + 1, dtype=torch.int64, device="cuda")
+    Bd = to_dev(BhT, words(k) + 1)
+    Cd = empty_dev(m, words(n))
+    announce("alt_basis_io transposed B")
+    bmm.bmm_gf2_strassen(to_dev(Ah), Bd, Cd, m, k, n, ws, depth=d, options=opts,
+                         alt_basis_io=True, b_transposed=True)
+    assert np.array_equal(from_dev(Cd), want_hat)
+    assert np.array_equal(from_dev(Bd, words(k)), BhT)
+
+
 def test_strassen_errors(bmm):
     import torch
     A = empty_dev(1024, 16)
@@ -316,3 +454,8 @@ def test_strassen_errors(bmm):
     with pytest.raises(bmm.BmmError) as e:
         bmm.bmm_gf2_strassen(A, empty_dev(1024, 16), C, 1024, 1024, 1024, ws, depth=2)
     assert e.value.status == -3  # workspace too small
+    big = torch.empty(1 << 22, dtype=torch.int64, device="cuda")
+    with pytest.raises(bmm.BmmError) as e:  # in place with B^T inside A's storage
+        bmm.bmm_gf2_strassen(A, A[:, :], C, 1024, 1024, 1024, big, depth=2, b_transposed=True,
+                             inplace_basis=True)
+    assert e.value.status == -1
