@@ -28,6 +28,11 @@ typedef const BMM_GLOBAL char* gc_ptr;
 typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
 
 constexpr int RA = 4, RB = 2;        // 128 x 64 wave tile, as the recursion's int8 leaf
+
+// Zero words that the second load of a weight-1 combination reads instead of a
+// parent quadrant (one row of k <= 4096 bits; every lane reads the same few lines,
+// so these loads hit in the vector L1 and cost no L2 traffic).
+__device__ __align__(256) uint64_t zero_words[64];
 constexpr int TM = 32 * RA, TN = 32 * RB;
 constexpr int kWaves = 4;
 
@@ -65,9 +70,9 @@ __device__ __forceinline__ uint32_t out_mask(int q) {
   return r;
 }
 
-// Word offsets of the (at most two) parent quadrants a child operand sums, and the
-// mask applied to the second load (all ones for weight 2, zero for weight 1, where
-// the second load repeats the first address).
+// Word offsets of the (at most two) parent quadrants a child operand sums; mask1 is
+// nonzero for weight 2 (the second quadrant is loaded and XORed in; for weight 1 the
+// second load reads zero words).
 struct Pick {
   int64_t off0, off1;
   uint64_t mask1;
@@ -132,36 +137,40 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void l
   uint64_t ua[KV][RA], va[KV][RA], ub[KV][RB], vb[KV][RB];  // raw words in flight
   uint64_t xa[KV][RA], xb[KV][RB];                          // the step's operands
 
+  const uint32_t zoff = (uint32_t)(KV * half * 8);
   auto fetch = [&](const Pick& pa, const Pick& pb, int st) {
     const int64_t wd = (int64_t)st * 2 * KV;
-    const gc_ptr a0 = (gc_ptr)(tbase + pa.off0 + wd), a1 = (gc_ptr)(tbase + pa.off1 + wd);
-    const gc_ptr b0 = (gc_ptr)(sbase + pb.off0 + wd), b1 = (gc_ptr)(sbase + pb.off1 + wd);
+    const gc_ptr a0 = (gc_ptr)(tbase + pa.off0 + wd), b0 = (gc_ptr)(sbase + pb.off0 + wd);
+    const gc_ptr a1 = pa.mask1 ? (gc_ptr)(tbase + pa.off1 + wd) : (gc_ptr)(zero_words + wd);
+    const gc_ptr b1 = pb.mask1 ? (gc_ptr)(sbase + pb.off1 + wd) : (gc_ptr)(zero_words + wd);
 #pragma unroll
     for (int f = 0; f < RA; ++f) {
+      const uint32_t o1 = pa.mask1 ? arow[f] : zoff;
       if constexpr (KV == 2) {
         const u64x2 u = *reinterpret_cast<const BMM_GLOBAL u64x2*>(a0 + arow[f]);
-        const u64x2 v = *reinterpret_cast<const BMM_GLOBAL u64x2*>(a1 + arow[f]);
+        const u64x2 v = *reinterpret_cast<const BMM_GLOBAL u64x2*>(a1 + o1);
         ua[0][f] = u.x;
         ua[1][f] = u.y;
         va[0][f] = v.x;
         va[1][f] = v.y;
       } else {
         ua[0][f] = *reinterpret_cast<const BMM_GLOBAL uint64_t*>(a0 + arow[f]);
-        va[0][f] = *reinterpret_cast<const BMM_GLOBAL uint64_t*>(a1 + arow[f]);
+        va[0][f] = *reinterpret_cast<const BMM_GLOBAL uint64_t*>(a1 + o1);
       }
     }
 #pragma unroll
     for (int g = 0; g < RB; ++g) {
+      const uint32_t o1 = pb.mask1 ? brow[g] : zoff;
       if constexpr (KV == 2) {
         const u64x2 u = *reinterpret_cast<const BMM_GLOBAL u64x2*>(b0 + brow[g]);
-        const u64x2 v = *reinterpret_cast<const BMM_GLOBAL u64x2*>(b1 + brow[g]);
+        const u64x2 v = *reinterpret_cast<const BMM_GLOBAL u64x2*>(b1 + o1);
         ub[0][g] = u.x;
         ub[1][g] = u.y;
         vb[0][g] = v.x;
         vb[1][g] = v.y;
       } else {
         ub[0][g] = *reinterpret_cast<const BMM_GLOBAL uint64_t*>(b0 + brow[g]);
-        vb[0][g] = *reinterpret_cast<const BMM_GLOBAL uint64_t*>(b1 + brow[g]);
+        vb[0][g] = *reinterpret_cast<const BMM_GLOBAL uint64_t*>(b1 + o1);
       }
     }
   };
@@ -169,9 +178,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void l
 #pragma unroll
     for (int v = 0; v < KV; ++v) {
 #pragma unroll
-      for (int f = 0; f < RA; ++f) xa[v][f] = ua[v][f] ^ (va[v][f] & pa.mask1);
+      for (int f = 0; f < RA; ++f) xa[v][f] = ua[v][f] ^ va[v][f];
 #pragma unroll
-      for (int g = 0; g < RB; ++g) xb[v][g] = ub[v][g] ^ (vb[v][g] & pb.mask1);
+      for (int g = 0; g < RB; ++g) xb[v][g] = ub[v][g] ^ vb[v][g];
     }
   };
 
