@@ -518,9 +518,15 @@ def run_ooc(args, torch, np, bmm, bmmgen):
         else:
             h2d = 2 * g ** 3 * block_bytes
             d2h = n * n / 8
+        hb, hs, db, dsec = bmm.bmm_ooc_last_transfers()
         out[name] = {"seconds": round(secs, 3), "pbops": round(2.0 * n ** 3 / secs / 1e15, 4),
                      "h2d_bytes": h2d, "d2h_bytes": d2h,
-                     "pcie_gbs": round((h2d + d2h) / secs / 1e9, 2),
+                     "pcie_gbs_wall": round((h2d + d2h) / secs / 1e9, 2),
+                     # the copies' own durations (HIP events around each on its stream)
+                     "h2d_copy_bytes": hb, "h2d_copy_s": round(hs, 4),
+                     "h2d_gbs": round(hb / hs / 1e9, 2) if hs > 0 else None,
+                     "d2h_copy_bytes": db, "d2h_copy_s": round(dsec, 4),
+                     "d2h_gbs": round(db / dsec / 1e9, 2) if dsec > 0 else None,
                      "verified_rows": len(rows), "verified": bool(np.array_equal(got, want))}
         log(f"[bench] ooc {name}: {secs:.2f} s {out[name]}")
     del A, B, C, slab

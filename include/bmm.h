@@ -257,6 +257,14 @@ int bmm_ooc(int semiring, const uint64_t* A, int64_t lda, const uint64_t* B, int
             uint64_t* C, int64_t ldc, int64_t m, int64_t k, int64_t n, int64_t block,
             const bmm_options* opt, double* seconds_out);
 
+/* Host <-> device transfers of the calling thread's last successful bmm_ooc call
+ * (also when reached through BMM_FLAG_HOST_OPERANDS), per direction: bytes moved
+ * and the summed durations of the copies themselves (HIP events around each copy
+ * on its own stream), so bytes / seconds is the PCIe rate while data moves.  Any
+ * pointer may be NULL; zeros before the first call. */
+int bmm_ooc_last_transfers(double* h2d_bytes, double* h2d_seconds, double* d2h_bytes,
+                           double* d2h_seconds);
+
 /* Stage entry points of the recursion (for kernel-by-kernel checks and for
  * callers that build their own schedules).  All enqueue on hip_stream.
  *
@@ -362,6 +370,13 @@ int bmm_calibrate_valu(int waves_per_simd, int64_t rounds, double* lane_ops_per_
 int bmm_cubic_noalloc(int semiring, const uint64_t* A, int64_t lda, const uint64_t* B,
                       int64_t ldb, uint64_t* C, int64_t ldc, int64_t m, int64_t k, int64_t n,
                       const bmm_options* opt, void* hip_stream);
+
+/* Testing hook: the next `count` device allocations the library makes (scratch,
+ * plans, staging, out-of-core buffers, autotuner buffers) fail as if the device
+ * were out of memory, so callers' error paths can be exercised; the entry point
+ * then returns BMM_E_NOMEM and leaves no allocation behind.  count <= 0 disarms.
+ * Process-wide. */
+int bmm_debug_fail_allocations(int64_t count);
 
 const char* bmm_status_string(int status);
 const char* bmm_last_error(void);

@@ -35,9 +35,11 @@ _lib = None
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_build.SO):
+        # ORACLE_LIBRARY: a sanitized build of the same C file (host-logic CPU tests)
+        so = os.environ.get("ORACLE_LIBRARY") or _build.SO
+        if not os.path.exists(so):
             _build.build()
-        lib = ctypes.CDLL(_build.SO)
+        lib = ctypes.CDLL(so)
         i64 = ctypes.c_int64
         vp = ctypes.c_void_p
         lib.oracle_rows.argtypes = [ctypes.c_int, vp, i64, i64, vp, i64, vp, i64, i64, i64]

@@ -26,6 +26,7 @@ __all__ = [
     "bmm_autotune_strassen", "bmm_autotune_set", "bmm_autotune_batched", "bmm_autotune_save",
     "bmm_autotune_load", "bmm_leaf_tiles", "bmm_leaf_tile_shape", "bmm_leaf_choice", "bmm_version",
     "bmm_finalize", "library_path", "bmm_calibrate_valu", "bmm_cubic_noalloc",
+    "bmm_ooc_last_transfers", "bmm_debug_fail_allocations",
 ]
 
 GF2, BOOLEAN = 0, 1
@@ -48,15 +49,20 @@ class BmmError(RuntimeError):
         self.status = status
 
 
+# BMM_LIBRARY names another build of the library (the host-only sanitized build of
+# build_sanitized.py, for CPU tests of the host logic); the default is the product build.
+_SO = os.environ.get("BMM_LIBRARY") or _build.SO
+
+
 def library_path():
-    return _build.SO
+    return _SO
 
 
-if not os.path.exists(_build.SO):
-    raise ImportError(f"{_build.SO} is not built; run __graft_entry__.build() "
+if not os.path.exists(_SO):
+    raise ImportError(f"{_SO} is not built; run __graft_entry__.build() "
                       "(python -m paper_1909_01554_amd.build)")
 
-_lib = ctypes.CDLL(_build.SO)
+_lib = ctypes.CDLL(_SO)
 _i64 = ctypes.c_int64
 _vp = ctypes.c_void_p
 _int = ctypes.c_int
@@ -129,6 +135,8 @@ _c_tiles = _sig("bmm_leaf_tiles", [_int, ctypes.POINTER(_int)])
 _c_tile_shape = _sig("bmm_leaf_tile_shape", [_int, _int, ctypes.POINTER(_int),
                                              ctypes.POINTER(_int)])
 _c_calib = _sig("bmm_calibrate_valu", [_int, _i64] + [ctypes.POINTER(ctypes.c_double)] * 4)
+_c_ooc_xfer = _sig("bmm_ooc_last_transfers", [ctypes.POINTER(ctypes.c_double)] * 4)
+_c_fail_allocs = _sig("bmm_debug_fail_allocations", [_i64])
 _c_last_error = _sig("bmm_last_error", [], ctypes.c_char_p)
 _c_version = _sig("bmm_version", [], ctypes.c_char_p)
 _c_finalize = _sig("bmm_finalize", [], None)
@@ -455,6 +463,18 @@ def bmm_ooc(semiring, A, B, C, m, k, n, block=0, options=None):
     _check(_c_ooc(semiring, a, lda, b, ldb, c, ldc, m, k, n, block, ctypes.byref(o),
                   ctypes.byref(secs)))
     return secs.value
+
+
+def bmm_debug_fail_allocations(count):
+    """Make the library's next `count` device allocations fail (0 disarms)."""
+    _check(_c_fail_allocs(count))
+
+
+def bmm_ooc_last_transfers():
+    """(h2d_bytes, h2d_seconds, d2h_bytes, d2h_seconds) of this thread's last bmm_ooc."""
+    out = [ctypes.c_double(0.0) for _ in range(4)]
+    _check(_c_ooc_xfer(*[ctypes.byref(v) for v in out]))
+    return tuple(v.value for v in out)
 
 
 def bmm_autotune_cubic(semiring, m, k, n):

@@ -25,6 +25,22 @@ thread_local std::string g_last_error;
 }  // namespace
 
 namespace bmm {
+
+// Allocation-failure hook for tests: while positive, every library device allocation
+// fails as if the device were out of memory, and the count drops by one.
+std::atomic<int64_t> g_fail_allocs{0};
+
+hipError_t dev_malloc(void** p, size_t bytes) {
+  int64_t left = g_fail_allocs.load();
+  while (left > 0) {
+    if (g_fail_allocs.compare_exchange_weak(left, left - 1)) {
+      *p = nullptr;
+      return hipErrorOutOfMemory;
+    }
+  }
+  return hipMalloc(p, bytes);
+}
+
 int set_error(int code, const char* fmt, ...) {
   char buf[512];
   va_list ap;
@@ -94,7 +110,7 @@ int scratch(size_t bytes, void** out) {
     }
     size_t want = std::max(bytes, (size_t)1 << 20);
     void* p = nullptr;
-    if (hipMalloc(&p, want) != hipSuccess || !p) {
+    if (dev_malloc(&p, want) != hipSuccess || !p) {
       (void)hipGetLastError();
       return fail(BMM_E_NOMEM, "scratch allocation of %zu bytes failed", want);
     }
@@ -850,8 +866,8 @@ int bmm_autotune_leaf(int semiring, int64_t m, int64_t k, int64_t n, int64_t bat
   const int64_t nb = batch_bucket(batch);  // time on the bucket's batch size
   uint64_t *A = nullptr, *BT = nullptr, *C = nullptr;
   const size_t ba = (size_t)m * kw * 8, bb = (size_t)n * kw * 8, bc = (size_t)m * nw * 8;
-  if (hipMalloc((void**)&A, ba * nb) != hipSuccess || hipMalloc((void**)&BT, bb * nb) != hipSuccess ||
-      hipMalloc((void**)&C, bc * nb) != hipSuccess) {
+  if (dev_malloc((void**)&A, ba * nb) != hipSuccess || dev_malloc((void**)&BT, bb * nb) != hipSuccess ||
+      dev_malloc((void**)&C, bc * nb) != hipSuccess) {
     (void)hipGetLastError();
     (void)hipFree(A);
     (void)hipFree(BT);
@@ -1091,6 +1107,11 @@ const char* bmm_status_string(int status) {
 const char* bmm_last_error(void) { return g_last_error.c_str(); }
 
 const char* bmm_version(void) { return "bmm 0.1 (gfx950)"; }
+
+int bmm_debug_fail_allocations(int64_t count) {
+  g_fail_allocs.store(count > 0 ? count : 0);
+  return BMM_OK;
+}
 
 void bmm_finalize(void) {
   batched_cache_clear();

@@ -206,9 +206,9 @@ int build_plan(const bmm_problem* problems, int64_t count, const bmm_options* op
   P.grid = std::max(kXcds, cus * wg_per_cu);
   if (P.count > 0) {
     const size_t cbytes = sizeof(unsigned int) * kXcds * kBatchedCounterStride;
-    if (hipMalloc((void**)&P.descs, sizeof(BatchedDesc) * host.size()) != hipSuccess ||
-        hipMalloc((void**)&P.segs, sizeof(BatchedSeg) * segs.size()) != hipSuccess ||
-        hipMalloc((void**)&P.counters, cbytes) != hipSuccess) {
+    if (bmm::dev_malloc((void**)&P.descs, sizeof(BatchedDesc) * host.size()) != hipSuccess ||
+        bmm::dev_malloc((void**)&P.segs, sizeof(BatchedSeg) * segs.size()) != hipSuccess ||
+        bmm::dev_malloc((void**)&P.counters, cbytes) != hipSuccess) {
       (void)hipGetLastError();
       (void)hipFree(P.descs);
       (void)hipFree(P.segs);
@@ -296,7 +296,7 @@ struct BatchedEntry {
     for (const auto& q : key)
       if (!q.b_transposed && q.m > 0 && q.n > 0 && q.k > 0)
         need += (size_t)q.n * ((q.k + 63) / 64) * 8;
-    if (need && hipMalloc((void**)&stage, need) != hipSuccess) {
+    if (need && bmm::dev_malloc((void**)&stage, need) != hipSuccess) {
       (void)hipGetLastError();
       stage = nullptr;
       return bfail(BMM_E_NOMEM, "batched staging of %zu bytes", need);

@@ -15,6 +15,10 @@ enum Semiring { GF2 = 0, BOOLEAN = 1 };
 // Record a message for bmm_last_error() (thread-local) and return `code`.
 int set_error(int code, const char* fmt, ...);
 
+// Every device allocation the library makes goes through here (hipMalloc, or a
+// forced failure while bmm_debug_fail_allocations is armed).
+hipError_t dev_malloc(void** p, size_t bytes);
+
 // A dispatch covers fewer than 2^32 work-items (the grid size of an AQL packet is
 // 32 bits).  Launchers whose grid would reach that return kGridTooLarge without
 // launching; the entry points report it as BMM_E_UNSUPPORTED.

@@ -92,8 +92,8 @@ extern "C" int bmm_calibrate_valu(int waves_per_simd, int64_t rounds, double* la
   const int waves = blocks * 4;
   uint32_t* sink = nullptr;
   long long* stamps = nullptr;
-  if (hipMalloc((void**)&sink, (size_t)blocks * 256 * 4) != hipSuccess ||
-      hipMalloc((void**)&stamps, (size_t)waves * 4 * sizeof(long long)) != hipSuccess) {
+  if (bmm::dev_malloc((void**)&sink, (size_t)blocks * 256 * 4) != hipSuccess ||
+      bmm::dev_malloc((void**)&stamps, (size_t)waves * 4 * sizeof(long long)) != hipSuccess) {
     (void)hipGetLastError();
     (void)hipFree(sink);
     return set_error(BMM_E_NOMEM, "calibration buffers");

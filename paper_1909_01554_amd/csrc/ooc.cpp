@@ -55,6 +55,54 @@ bool is_pinned(const void* p) {
   return attr.type == hipMemoryTypeHost;
 }
 
+// Host <-> device copy times, per direction: HIP events on the copy's own stream
+// bracket every transfer, so each rate is bytes over the copies' own durations (the
+// PCIe link's rate while it moves data), not over the product's wall time.
+struct CopyLog {
+  struct Xfer {
+    hipEvent_t e0, e1;
+    double bytes;
+    int d2h;
+  };
+  std::vector<Xfer> xs;
+  int begin(hipStream_t s) {
+    Xfer x{nullptr, nullptr, 0.0, 0};
+    if (hipEventCreate(&x.e0) != hipSuccess || hipEventCreate(&x.e1) != hipSuccess) {
+      if (x.e0) (void)hipEventDestroy(x.e0);
+      return ofail(BMM_E_DEVICE, "copy timing event");
+    }
+    xs.push_back(x);
+    return hip_ok(hipEventRecord(x.e0, s), "record");
+  }
+  int end(hipStream_t s, double bytes, int d2h) {
+    xs.back().bytes = bytes;
+    xs.back().d2h = d2h;
+    return hip_ok(hipEventRecord(xs.back().e1, s), "record");
+  }
+  // after every copy has finished
+  void totals(double* h2d_b, double* h2d_s, double* d2h_b, double* d2h_s) const {
+    *h2d_b = *h2d_s = *d2h_b = *d2h_s = 0.0;
+    for (const Xfer& x : xs) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, x.e0, x.e1) != hipSuccess) {
+        (void)hipGetLastError();
+        continue;
+      }
+      (x.d2h ? *d2h_b : *h2d_b) += x.bytes;
+      (x.d2h ? *d2h_s : *h2d_s) += ms * 1e-3;
+    }
+  }
+  ~CopyLog() {
+    for (const Xfer& x : xs) {
+      (void)hipEventDestroy(x.e0);
+      if (x.e1) (void)hipEventDestroy(x.e1);
+    }
+  }
+};
+
+// Per-direction transfer totals of the calling thread's last bmm_ooc call.
+thread_local double g_xfer[4] = {0.0, 0.0, 0.0, 0.0};
+
 struct Resources {
   hipStream_t copy = nullptr, comp = nullptr, down = nullptr;
   hipEvent_t loaded[2] = {nullptr, nullptr}, used[2] = {nullptr, nullptr};
@@ -160,7 +208,7 @@ struct HostRes {
 // HBM does not admit it, else a bmm status.
 int ooc_host_levels(const uint64_t* A, int64_t lda, const uint64_t* B, int64_t ldb,
                     uint64_t* C, int64_t ldc, int64_t n, int64_t b, const bmm_options& o,
-                    int leaf) {
+                    int leaf, CopyLog& log) {
   if (n % b || n / b < 2 || b % 64) return 1;
   int dh = 0;
   while (((int64_t)b << dh) < n) ++dh;
@@ -203,16 +251,16 @@ int ooc_host_levels(const uint64_t* A, int64_t lda, const uint64_t* B, int64_t l
   for (int i = 0; i < 2; ++i) {
     for (hipEvent_t* e : {&R.loaded[i], &R.freed[i], &R.ready[i], &R.done[i]})
       OOC_TRY(hip_ok(hipEventCreateWithFlags(e, hipEventDisableTiming), "event"));
-    if (hipMalloc((void**)&R.stage[i], blk) != hipSuccess ||
-        hipMalloc((void**)&R.T[i], blk) != hipSuccess ||
-        hipMalloc((void**)&R.ST[i], blk) != hipSuccess) {
+    if (bmm::dev_malloc((void**)&R.stage[i], blk) != hipSuccess ||
+        bmm::dev_malloc((void**)&R.T[i], blk) != hipSuccess ||
+        bmm::dev_malloc((void**)&R.ST[i], blk) != hipSuccess) {
       (void)hipGetLastError();
       return ofail(BMM_E_NOMEM, "out-of-core host-level buffers");
     }
   }
-  if (hipMalloc((void**)&R.btmp, blk) != hipSuccess || hipMalloc((void**)&R.Q, blk) != hipSuccess ||
-      hipMalloc((void**)&R.Chat, (size_t)n * nw * 8) != hipSuccess ||
-      (ws_bytes && hipMalloc(&R.ws, ws_bytes) != hipSuccess)) {
+  if (bmm::dev_malloc((void**)&R.btmp, blk) != hipSuccess || bmm::dev_malloc((void**)&R.Q, blk) != hipSuccess ||
+      bmm::dev_malloc((void**)&R.Chat, (size_t)n * nw * 8) != hipSuccess ||
+      (ws_bytes && bmm::dev_malloc(&R.ws, ws_bytes) != hipSuccess)) {
     (void)hipGetLastError();
     return ofail(BMM_E_NOMEM, "out-of-core host-level buffers");
   }
@@ -231,9 +279,11 @@ int ooc_host_levels(const uint64_t* A, int64_t lda, const uint64_t* B, int64_t l
           if (up >= 2) OOC_TRY(hip_ok(hipStreamWaitEvent(R.copy, R.freed[s], 0), "wait"));
           const uint64_t* src = side == 0 ? A + r * b * lda + c * bw : B + r * b * ldb + c * bw;
           const int64_t ld = side == 0 ? lda : ldb;
+          OOC_TRY(log.begin(R.copy));
           OOC_TRY(hip_ok(hipMemcpy2DAsync(R.stage[s], bw * 8, src, ld * 8, bw * 8, b,
                                           hipMemcpyHostToDevice, R.copy),
                          "H2D block"));
+          OOC_TRY(log.end(R.copy, (double)blk, 0));
           OOC_TRY(hip_ok(hipEventRecord(R.loaded[s], R.copy), "record"));
           OOC_TRY(hip_ok(hipStreamWaitEvent(R.comb, R.loaded[s], 0), "wait"));
           const uint64_t* add = R.stage[s];
@@ -268,10 +318,13 @@ int ooc_host_levels(const uint64_t* A, int64_t lda, const uint64_t* B, int64_t l
   }
   OOC_TRY(hip_ok(launch_basis(R.Chat, nw, 0, n, nw, 1, dh + d, 1, R.comp, o.scheme, 0),
                  "basis C"));
+  OOC_TRY(log.begin(R.comp));
   OOC_TRY(hip_ok(hipMemcpy2DAsync(C, ldc * 8, R.Chat, nw * 8, nw * 8, n, hipMemcpyDeviceToHost,
                                   R.comp),
                  "D2H C"));
+  OOC_TRY(log.end(R.comp, (double)n * nw * 8, 1));
   OOC_TRY(hip_ok(hipStreamSynchronize(R.comp), "sync"));
+  OOC_TRY(hip_ok(hipStreamSynchronize(R.copy), "sync"));
   return BMM_OK;
 }
 
@@ -312,13 +365,18 @@ extern "C" int bmm_ooc(int semiring, const uint64_t* A, int64_t lda, const uint6
   }
 
   const auto t0 = std::chrono::steady_clock::now();
+  for (double& x : g_xfer) x = 0.0;
+  CopyLog log;
   if (semiring == BMM_GF2 && !(o.flags & BMM_FLAG_OOC_BLOCK_ORDER) &&
       !(o.depth_serial == 0 && o.depth_parallel == 0) && m == k && k == n) {
-    const int rc = ooc_host_levels(A, lda, B, ldb, C, ldc, n, block, o, leaf);
+    const int rc = ooc_host_levels(A, lda, B, ldb, C, ldc, n, block, o, leaf, log);
     if (rc != 1) {
-      if (rc == BMM_OK && seconds_out)
-        *seconds_out =
-            std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      if (rc == BMM_OK) {
+        if (seconds_out)
+          *seconds_out =
+              std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        log.totals(&g_xfer[0], &g_xfer[1], &g_xfer[2], &g_xfer[3]);
+      }
       return rc;
     }
   }
@@ -331,14 +389,14 @@ extern "C" int bmm_ooc(int semiring, const uint64_t* A, int64_t lda, const uint6
     OOC_TRY(hip_ok(hipEventCreateWithFlags(&R.used[i], hipEventDisableTiming), "event"));
     OOC_TRY(hip_ok(hipEventCreateWithFlags(&R.cdone[i], hipEventDisableTiming), "event"));
     OOC_TRY(hip_ok(hipEventCreateWithFlags(&R.cfree[i], hipEventDisableTiming), "event"));
-    if (hipMalloc((void**)&R.a[i], (size_t)bm * bkw * 8) != hipSuccess ||
-        hipMalloc((void**)&R.b[i], (size_t)bk * bnw * 8) != hipSuccess ||
-        hipMalloc((void**)&R.c[i], (size_t)bm * bnw * 8) != hipSuccess) {
+    if (bmm::dev_malloc((void**)&R.a[i], (size_t)bm * bkw * 8) != hipSuccess ||
+        bmm::dev_malloc((void**)&R.b[i], (size_t)bk * bnw * 8) != hipSuccess ||
+        bmm::dev_malloc((void**)&R.c[i], (size_t)bm * bnw * 8) != hipSuccess) {
       (void)hipGetLastError();
       return ofail(BMM_E_NOMEM, "out-of-core HBM buffers for block %ld", (long)block);
     }
   }
-  if (hipMalloc((void**)&R.bt, (size_t)bn * bkw * 8) != hipSuccess) {
+  if (bmm::dev_malloc((void**)&R.bt, (size_t)bn * bkw * 8) != hipSuccess) {
     (void)hipGetLastError();
     return ofail(BMM_E_NOMEM, "out-of-core transpose buffer");
   }
@@ -353,7 +411,7 @@ extern "C" int bmm_ooc(int semiring, const uint64_t* A, int64_t lda, const uint6
     po.depth_serial = po.depth_parallel = -1;
     if (strassen_alt_plan(bm, bk, bn, -1, po, &ws_bytes, &d) != BMM_OK || d == 0) {
       ws_bytes = 0;
-    } else if (hipMalloc(&R.ws, ws_bytes) != hipSuccess) {
+    } else if (bmm::dev_malloc(&R.ws, ws_bytes) != hipSuccess) {
       (void)hipGetLastError();
       return ofail(BMM_E_NOMEM, "out-of-core Strassen workspace (%zu bytes)", ws_bytes);
     }
@@ -389,6 +447,7 @@ extern "C" int bmm_ooc(int semiring, const uint64_t* A, int64_t lda, const uint6
         const int s = (int)(step & 1);
         // upload the pair into slot s once its previous user has finished
         if (step >= 2) OOC_TRY(hip_ok(hipStreamWaitEvent(R.copy, R.used[s], 0), "wait"));
+        OOC_TRY(log.begin(R.copy));
         OOC_TRY(hip_ok(hipMemcpy2DAsync(R.a[s], bkw * 8, A + I * bm * lda + J * (bk / 64),
                                         lda * 8, dwords * 8, rows, hipMemcpyHostToDevice,
                                         R.copy),
@@ -397,6 +456,7 @@ extern "C" int bmm_ooc(int semiring, const uint64_t* A, int64_t lda, const uint6
                                         ldb * 8, cwords * 8, depth, hipMemcpyHostToDevice,
                                         R.copy),
                        "H2D B"));
+        OOC_TRY(log.end(R.copy, (double)(rows * dwords + depth * cwords) * 8, 0));
         OOC_TRY(hip_ok(hipEventRecord(R.loaded[s], R.copy), "record"));
         OOC_TRY(hip_ok(hipStreamWaitEvent(R.comp, R.loaded[s], 0), "wait"));
         OOC_TRY(hip_ok(launch_transpose(R.b[s], bnw, 0, R.bt, bkw, 0, depth, cols, 1, R.comp),
@@ -445,17 +505,30 @@ extern "C" int bmm_ooc(int semiring, const uint64_t* A, int64_t lda, const uint6
                        "basis C"));
       OOC_TRY(hip_ok(hipEventRecord(R.cdone[cs], R.comp), "record"));
       OOC_TRY(hip_ok(hipStreamWaitEvent(R.down, R.cdone[cs], 0), "wait"));
+      OOC_TRY(log.begin(R.down));
       OOC_TRY(hip_ok(hipMemcpy2DAsync(C + I * bm * ldc + K * (bn / 64), ldc * 8, R.c[cs],
                                       bnw * 8, cwords * 8, rows, hipMemcpyDeviceToHost,
                                       R.down),
                      "D2H C"));
+      OOC_TRY(log.end(R.down, (double)rows * cwords * 8, 1));
       OOC_TRY(hip_ok(hipEventRecord(R.cfree[cs], R.down), "record"));
       ++cblock;
     }
   }
   OOC_TRY(hip_ok(hipStreamSynchronize(R.comp), "sync"));
   OOC_TRY(hip_ok(hipStreamSynchronize(R.down), "sync"));
+  OOC_TRY(hip_ok(hipStreamSynchronize(R.copy), "sync"));
   const auto t1 = std::chrono::steady_clock::now();
   if (seconds_out) *seconds_out = std::chrono::duration<double>(t1 - t0).count();
+  log.totals(&g_xfer[0], &g_xfer[1], &g_xfer[2], &g_xfer[3]);
+  return BMM_OK;
+}
+
+extern "C" int bmm_ooc_last_transfers(double* h2d_bytes, double* h2d_seconds,
+                                      double* d2h_bytes, double* d2h_seconds) {
+  if (h2d_bytes) *h2d_bytes = g_xfer[0];
+  if (h2d_seconds) *h2d_seconds = g_xfer[1];
+  if (d2h_bytes) *d2h_bytes = g_xfer[2];
+  if (d2h_seconds) *d2h_seconds = g_xfer[3];
   return BMM_OK;
 }

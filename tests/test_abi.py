@@ -199,3 +199,11 @@ def test_launch_grid_bound():
         rc = bmm._c_gf2(vp(A), 1, vp(B), 1, vp(C), n // 64, m, k, n, ctypes.byref(o), None)
         assert rc == -2, (leaf, tile, rc)
         assert "2^32" in bmm._c_last_error().decode()
+
+
+def test_allocation_failure_hook_arms_and_disarms():
+    """The testing hook is exported and takes any count; a negative count disarms."""
+    import paper_1909_01554_amd as bmm
+    bmm.bmm_debug_fail_allocations(3)
+    bmm.bmm_debug_fail_allocations(-1)
+    bmm.bmm_debug_fail_allocations(0)

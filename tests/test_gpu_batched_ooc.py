@@ -157,6 +157,11 @@ def test_ooc_small(bmm, sr):
     assert secs > 0
     got = Ch.numpy().view(np.uint64)
     assert np.array_equal(got, oracle.mul(A, B, k, n, sr))
+    # every C word crosses PCIe down once; each A block goes up once per column block
+    # of C (4 of them) and each B block once per row block of C (3)
+    hb, hs, db, ds = bmm.bmm_ooc_last_transfers()
+    assert db == m * words(n) * 8 and ds > 0
+    assert hb == 4 * A.nbytes + 3 * B.nbytes and hs > 0
 
 
 @pytest.mark.parametrize("cubic_only", [False, True])
