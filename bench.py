@@ -256,7 +256,7 @@ def run_batched(args, torch, np, bmm, bmmgen):
     # every (leaf, tile) candidate timed once for the record, then the autotuner's choice
     cands = {}
     for lf, lname in [(bmm.LEAF_MFMA_I8, "int8"), (bmm.LEAF_MFMA_F4, "fp4")]:
-        for tl, tname in [(1, "128x64"), (2, "64x64"), (3, "64x128")]:
+        for tl, tname in [(1, "128x64"), (2, "64x64"), (3, "64x128"), (4, "128x64lds")]:
             pl = bmm.BatchedPlan(probs, options=bmm.Options(leaf=lf, tile=tl))
             pl.launch()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -322,7 +322,7 @@ def run_batched(args, torch, np, bmm, bmmgen):
         "one_launch_per_product_pbops": round(bops / t_loop / 1e15, 4),
         "speedup": round(t_loop / t_graph, 3), "verified_16_problems": ok,
         "autotuned": {"leaf": {2: "int8", 3: "fp4"}[leaf],
-                      "tile": {1: "128x64", 2: "64x64", 3: "64x128"}[tile]},
+                      "tile": {1: "128x64", 2: "64x64", 3: "64x128", 4: "128x64lds"}[tile]},
         "candidates_s": cands,
         "frac_of_peak": round(bops / t_graph / 1e12 / (PEAK_MFMA_F4_TOPS if leaf == 3
                                                         else PEAK_MFMA_I8_TOPS), 4)}), flush=True)
@@ -616,7 +616,10 @@ def main():
                           "copy_s": e[1].elapsed_time(e[2]) / 1e3}), flush=True)
         return
 
-    nbytes, ds, dp = bmm.bmm_gf2_strassen_workspace(n, n, n, args.depth, opts(bmm.LEAF_MFMA_I8))
+    # the GF(2) product changes A to the alternative basis in place and restores it
+    # (BMM_FLAG_INPLACE_BASIS): no 8 GiB copy of A in the workspace
+    nbytes, ds, dp = bmm.bmm_gf2_strassen_workspace(n, n, n, args.depth, opts(bmm.LEAF_MFMA_I8),
+                                                    inplace_basis=True)
     if args.mode == "tune":
         # room for the deeper plans the depth tuner tries
         nbytes = max(nbytes, bmm.bmm_gf2_strassen_workspace(
@@ -658,8 +661,9 @@ def main():
             out[f"strassen_leaf_{s_}"] = {"leaf": leaf, "tile": tile, "s": secs}
             log(f"[bench] tuned leaf {s_}^3 x64: leaf={leaf} tile={tile} {secs * 1e3:.2f} ms")
         # the depth tuner times the int8-MFMA leaf (the headline leaf)
-        d, dsel, shift, secs = bmm.bmm_autotune_strassen(Ag, Bg, Cg, n, n, n, ws,
-                                                  options=bmm.Options(leaf=bmm.LEAF_MFMA_I8))
+        d, dsel, shift, secs = bmm.bmm_autotune_strassen(
+            Ag, Bg, Cg, n, n, n, ws,
+            options=bmm.Options(leaf=bmm.LEAF_MFMA_I8, flags=bmm.FLAG_INPLACE_BASIS))
         out["strassen_depth"] = {"depth": d, "depth_serial": dsel, "shift": shift,
                                  "seconds": secs}
         log(f"[bench] tuned Strassen depth {d} (serial {dsel}, shift {shift}) {secs:.3f} s")
@@ -675,7 +679,8 @@ def main():
         o = opts(leaf)
         if ev:
             ev[0].record(stream)
-        bmm.bmm_gf2_strassen(Ag, Bg, Cg, n, n, n, ws, depth=args.depth, options=o)
+        bmm.bmm_gf2_strassen(Ag, Bg, Cg, n, n, n, ws, depth=args.depth, options=o,
+                             inplace_basis=True)
         if ev:
             ev[1].record(stream)
         bmm.bmm_transpose(Bb, BTb, n, n)
@@ -764,7 +769,8 @@ def main():
             o.scheme = sch
             e = events()
             e[0].record(stream)
-            bmm.bmm_gf2_strassen(Ag, Bg, Cg, n, n, n, ws, depth=args.depth, options=o)
+            bmm.bmm_gf2_strassen(Ag, Bg, Cg, n, n, n, ws, depth=args.depth, options=o,
+                             inplace_basis=True)
             e[1].record(stream)
             torch.cuda.synchronize()
             t = e[0].elapsed_time(e[1]) / 1e3
