@@ -227,13 +227,14 @@ int bmm_batched_plan_launch(void* plan, void* hip_stream);
 void bmm_batched_plan_destroy(void* plan);
 /* Leaf and tile of a batched plan: opt->leaf BMM_LEAF_MFMA_I8 or BMM_LEAF_MFMA_F4
  * (BMM_LEAF_VALU: BMM_E_UNSUPPORTED), opt->tile 1 (128 x 64 output tile per wave),
- * 2 (64 x 64) or 3 (64 x 128); 0 / AUTO take the autotuner's record for plans of the same
+ * 2 (64 x 64), 3 (64 x 128) or 4 (128 x 64 with the workgroup's operand rows staged
+ * through LDS and shared by its four waves); 0 / AUTO take the autotuner's record for plans of the same
  * problem count and total work (to a factor of two), else int8 with 64 x 64.  The
  * persistent grid (workgroups per CU) comes from the same record, else 4. */
 
 /* Autotuner for batched plans (the paper's empirical parameter choice,
  * section 3.17, applied to the persistent launch): times one launch of the plan
- * for every leaf kind (int8, fp4), tile (1, 2, 3) and persistent grid (2 or 4
+ * for every leaf kind (int8, fp4), tile (1, 2, 3, 4) and persistent grid (2 or 4
  * workgroups per CU) on the default stream, records the fastest for later
  * plans with AUTO options (saved by bmm_autotune_save), and returns its leaf
  * and tile.  Problems as for bmm_batched_plan_create; their outputs are

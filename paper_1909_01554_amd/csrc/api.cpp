@@ -1080,7 +1080,7 @@ int bmm_autotune_load(const char* path) {
     } else if (sscanf(line.c_str(), "batched %lld %d %d %d %d", &m, &d, &leaf, &t1, &t2) >= 4) {
       if (sscanf(line.c_str(), "batched %lld %d %d %d %d", &m, &d, &leaf, &t1, &t2) == 4) t2 = 4;
       if (m <= 0 || d < 0 || (leaf != BMM_LEAF_MFMA_I8 && leaf != BMM_LEAF_MFMA_F4) ||
-          t1 < 1 || t1 > 3 || t2 < 1 || t2 > 64)
+          t1 < 1 || t1 > 4 || t2 < 1 || t2 > 64)
         return fail(BMM_E_INVAL, "bad batched line: %s", line.c_str());
       std::lock_guard<std::mutex> lock(g_mu);
       g_batched[{m, d}] = {leaf, t1, t2};

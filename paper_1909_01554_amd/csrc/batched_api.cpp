@@ -130,7 +130,7 @@ int build_plan(const bmm_problem* problems, int64_t count, const bmm_options* op
   if (tile <= 0) tile = 2;
   if (leaf != BMM_LEAF_MFMA_I8 && leaf != BMM_LEAF_MFMA_F4)
     return bfail(BMM_E_UNSUPPORTED, "batched plans run the int8 or fp4 matrix-core leaf");
-  if (tile < 1 || tile > 3) return bfail(BMM_E_INVAL, "batched tile must be 1, 2 or 3");
+  if (tile < 1 || tile > 4) return bfail(BMM_E_INVAL, "batched tile must be 1, 2, 3 or 4");
   if (leaf == BMM_LEAF_MFMA_F4 && kmax >= ((int64_t)1 << 24))
     return bfail(BMM_E_UNSUPPORTED, "the fp4 leaf counts exactly only for k < 2^24");
   if (kmax >= ((int64_t)1 << 31))
@@ -408,7 +408,7 @@ int bmm_autotune_batched(const bmm_problem* problems, int64_t count, int* leaf_o
   double best = 1e30;
   int best_leaf = BMM_LEAF_MFMA_I8, best_tile = 2, best_wpc = 4, rc = BMM_OK;
   for (int leaf : {BMM_LEAF_MFMA_I8, BMM_LEAF_MFMA_F4}) {
-    for (int tile : {1, 2, 3}) {
+    for (int tile : {1, 2, 3, 4}) {
       for (int wpc : {2, 4}) {
         bmm_options o;
         bmm_options_init(&o);

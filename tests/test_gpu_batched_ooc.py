@@ -59,9 +59,10 @@ def test_batched_mixed(bmm, transposed):
 
 
 @pytest.mark.parametrize("leaf", [2, 3])
-@pytest.mark.parametrize("tile", [1, 2, 3])
+@pytest.mark.parametrize("tile", [1, 2, 3, 4])
 def test_batched_leaf_and_tile(bmm, leaf, tile):
-    """Every batched leaf kind (int8, fp4) and tile (128 x 64, 64 x 64, 64 x 128)."""
+    """Every batched leaf kind (int8, fp4) and tile (128 x 64, 64 x 64, 64 x 128, and
+    128 x 64 with LDS-shared operand rows)."""
     probs, host = make_problems(36, 50 + 3 * leaf + tile)
     announce("batched leaf/tile", leaf, tile)
     bmm.bmm_batched(probs, options=bmm.Options(leaf=leaf, tile=tile))
@@ -88,7 +89,7 @@ def large_batch():
 
 
 @pytest.mark.parametrize("leaf", [2, 3])
-@pytest.mark.parametrize("tile", [1, 2, 3])
+@pytest.mark.parametrize("tile", [1, 2, 3, 4])
 def test_batched_large_items(bmm, large_batch, leaf, tile):
     probs = []
     for sr, A, B, m, k, n, _ in large_batch:
@@ -105,7 +106,7 @@ def test_batched_autotune_and_auto_plan(bmm):
     probs, host = make_problems(24, 99)
     announce("batched autotune")
     leaf, tile, secs = bmm.bmm_autotune_batched(probs)
-    assert leaf in (2, 3) and tile in (1, 2, 3) and secs > 0
+    assert leaf in (2, 3) and tile in (1, 2, 3, 4) and secs > 0
     check(probs, host)
     for pr in probs:
         pr["C"].fill_(-1)
