@@ -95,123 +95,16 @@ __device__ __forceinline__ void run_item(const BatchedDesc& d, int64_t item, int
   }
 }
 
-// LDS-staged item (tile 4): the workgroup's 2 x 2 wave tiles of 128 x 64 cover
-// 256 rows of A and 128 rows of B^T; per stage of 8 words of k the four waves load
-// those 384 rows once, with 16-byte coalesced loads, into LDS (rows padded to 80
-// bytes so the lanes of one 16-byte LDS read hit distinct banks) and every wave reads
-// its own rows from there: each operand row is fetched from L2 once per workgroup
-// instead of once per wave that uses it.  The next stage is loaded into registers
-// while the current one computes.  Words past the end of k read as zero; whole
-// 4-word groups past it are skipped.  Every wave takes part in the loads and
-// barriers; waves whose tile lies outside the problem only skip the epilogue.
-constexpr int LS_KS = 8;                       // words of k per stage
-constexpr int LS_ROWB = 80;                    // padded LDS row (64 data bytes + 16)
-constexpr int LS_ROWS = 256 + 128;             // A rows, then B^T rows
-constexpr int LS_PANEL = LS_ROWS * LS_ROWB;    // bytes per stage buffer
-constexpr int LS_CHUNKS = LS_ROWS * 4 / 256;   // 16-byte chunks per thread per stage
-
+// LDS-staged item (tile 4): mfma::lds_item (operand rows of the workgroup's 2 x 2
+// wave tiles staged through LDS once per stage and shared by the four waves).
 template <int FMT>
 __device__ __forceinline__ void run_item_lds(const BatchedDesc& d, int64_t item, int w,
                                              unsigned char* smem) {
-  constexpr int RA = 4, RB = 2;
   int64_t im, in;
   band_coord(item, d.items_m, d.items_n, im, in);
-  const int tid = threadIdx.x, lane = tid & 63, half = lane >> 5, li = lane & 31;
-  const int64_t row0 = im * 256, col0 = in * 128;
-  const mfma::gq_ptr A = (mfma::gq_ptr)d.A;
-  const mfma::gq_ptr BT = (mfma::gq_ptr)d.BT;
-  const int64_t kw = (d.k + 63) >> 6;
-  // staging: chunk q = tid + 256 i covers row q >> 2, words 2 (q & 3) .. + 1 of a stage
-  mfma::gq_ptr src[LS_CHUNKS];
-  int soff[LS_CHUNKS], spart[LS_CHUNKS];
-#pragma unroll
-  for (int i = 0; i < LS_CHUNKS; ++i) {
-    const int q = tid + 256 * i;
-    const int r = q >> 2, part = q & 3;
-    spart[i] = part;
-    if (r < 256) {
-      int64_t g = row0 + r;
-      g = g < d.m ? g : d.m - 1;
-      src[i] = A + g * d.lda + 2 * part;
-    } else {
-      int64_t g = col0 + (r - 256);
-      g = g < d.n ? g : d.n - 1;
-      src[i] = BT + g * d.ldbt + 2 * part;
-    }
-    soff[i] = r * LS_ROWB + part * 16;
-  }
-  uint64_t stage[LS_CHUNKS][2];
-  auto load = [&](int64_t w0) {
-#pragma unroll
-    for (int i = 0; i < LS_CHUNKS; ++i) {
-      const int64_t wd = w0 + 2 * spart[i];
-      if (d.aligned && wd + 1 < kw) {
-        const ulonglong2 v = *reinterpret_cast<const ulonglong2*>((const uint64_t*)(src[i] + w0));
-        stage[i][0] = v.x;
-        stage[i][1] = v.y;
-      } else {
-        stage[i][0] = wd < kw ? src[i][w0] : 0ull;
-        stage[i][1] = wd + 1 < kw ? src[i][w0 + 1] : 0ull;
-      }
-    }
-  };
-  auto store = [&](int buf) {
-#pragma unroll
-    for (int i = 0; i < LS_CHUNKS; ++i) {
-      ulonglong2 v;
-      v.x = stage[i][0];
-      v.y = stage[i][1];
-      *reinterpret_cast<ulonglong2*>(smem + buf * LS_PANEL + soff[i]) = v;
-    }
-  };
-  using AccV = typename mfma::Acc<FMT>::type;
-  AccV acc[RA][RB];
-#pragma unroll
-  for (int f = 0; f < RA; ++f)
-#pragma unroll
-    for (int g = 0; g < RB; ++g) acc[f][g] = AccV{};
-  const int wy = w >> 1, wx = w & 1;
-  int aoff[RA], boff[RB];
-#pragma unroll
-  for (int f = 0; f < RA; ++f) aoff[f] = (wy * 128 + 32 * f + li) * LS_ROWB + 16 * half;
-#pragma unroll
-  for (int g = 0; g < RB; ++g) boff[g] = (256 + wx * 64 + 32 * g + li) * LS_ROWB + 16 * half;
-
-  const int64_t stages = (kw + LS_KS - 1) / LS_KS;
-  load(0);
-  store(0);
-  __syncthreads();
-  for (int64_t st = 0; st < stages; ++st) {
-    const int cur = (int)(st & 1);
-    if (st + 1 < stages) load((st + 1) * LS_KS);
-    const unsigned char* base = smem + cur * LS_PANEL;
-    // two groups of 4 words per stage: lane half h takes words 4s + 2h and 4s + 2h + 1
-#pragma unroll
-    for (int s2 = 0; s2 < LS_KS / 4; ++s2) {
-      if (st * LS_KS + 4 * s2 >= kw) break;  // uniform: only zero words are left
-      uint64_t xa[2][RA], xb[2][RB];
-#pragma unroll
-      for (int f = 0; f < RA; ++f) {
-        const ulonglong2 v = *reinterpret_cast<const ulonglong2*>(base + aoff[f] + 32 * s2);
-        xa[0][f] = v.x;
-        xa[1][f] = v.y;
-      }
-#pragma unroll
-      for (int g = 0; g < RB; ++g) {
-        const ulonglong2 v = *reinterpret_cast<const ulonglong2*>(base + boff[g] + 32 * s2);
-        xb[0][g] = v.x;
-        xb[1][g] = v.y;
-      }
-      mfma::mfma_word<mfma::SEMI_ANY, RA, RB, FMT, kWide>(xa[0], xb[0], acc);
-      mfma::mfma_word<mfma::SEMI_ANY, RA, RB, FMT, kWide>(xa[1], xb[1], acc);
-    }
-    if (st + 1 < stages) store(cur ^ 1);
-    __syncthreads();
-  }
-  const int64_t tm = 2 * im + wy, tn = 2 * in + wx;
-  if (tm < d.tiles_m && tn < d.tiles_n)
-    mfma::epilogue<mfma::SEMI_ANY, RA, RB, FMT>(acc, d.C, d.ldc, d.m, d.n, tm, tn, 0,
-                                                d.semiring);
+  mfma::lds_item<mfma::SEMI_ANY, FMT, kWide>(d.A, d.lda, d.BT, d.ldbt, d.C, d.ldc, d.m, d.k,
+                                             d.n, im, in, d.tiles_m, d.tiles_n, d.aligned != 0,
+                                             0, d.semiring, w, smem);
 }
 
 template <int FMT>
@@ -219,7 +112,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
     const BatchedDesc* __restrict__ descs, const BatchedSeg* __restrict__ segs,
     BatchedQueues qs, unsigned int* __restrict__ counters) {
   __shared__ int slots[2][2];
-  __shared__ __attribute__((aligned(16))) unsigned char smem[2 * LS_PANEL];
+  __shared__ __attribute__((aligned(16))) unsigned char smem[mfma::kLdsItemBytes];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   int q = blockIdx.x % kXcds, visited = 0;  // wave 0's queue state
   if (w == 0) {

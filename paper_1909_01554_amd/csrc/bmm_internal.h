@@ -83,6 +83,7 @@ enum MfmaTile { MFMA_128x64 = 0, MFMA_64x64 = 1, MFMA_64x128 = 2, MFMA_64x32 = 3
                 MFMA_LDS_256x256 = 4,
                 MFMA_DEEP_128x64 = 5,  // 128 x 64, 3-deep unrolled pipeline for k = 2048, 4096
                 MFMA_CHUNK_64x128 = 6,  // 64 x 128, 2-deep pipeline in unrolled 12-step chunks
+                MFMA_LDS4_256x128 = 7,  // 2 x 2 waves of 128 x 64, operand rows shared in LDS
                 MFMA_NUM_TILES };
 
 hipError_t launch_leaf_mfma(int semiring, const LeafBatch& p, int tile, hipStream_t s);

@@ -42,6 +42,36 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void l
                                     p.accumulate);
 }
 
+// The LDS-staged 2 x 2 wave item of mfma::lds_item, one per workgroup (tile 8): the
+// same 256 x 128 workgroup tiles, in the same XCD-aware order, with the operand rows of
+// each stage loaded once into LDS and shared by the four waves.
+template <int SEMI, int FMT, bool WIDE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void leaf_mfma_lds4_kernel(
+    LeafBatch p, int64_t tiles_m, int64_t tiles_n, int aligned) {
+  __shared__ __attribute__((aligned(16))) unsigned char smem[mfma::kLdsItemBytes];
+  const int64_t grid_m = (tiles_m + 1) >> 1, grid_n = (tiles_n + 1) >> 1;
+  const TileCoord c = xcd_tile(blockIdx.x, gridDim.x, grid_m, grid_n);
+  if (c.b >= p.batch) return;  // uniform per workgroup
+  mfma::lds_item<SEMI, FMT, WIDE>(p.A + c.b * p.strideA, p.lda, p.BT + c.b * p.strideB, p.ldbt,
+                                  p.C + c.b * p.strideC, p.ldc, p.m, p.k, p.n, c.tm, c.tn,
+                                  tiles_m, tiles_n, aligned != 0, p.accumulate, SEMI,
+                                  threadIdx.x >> 6, smem);
+}
+
+template <int SEMI, int FMT>
+hipError_t launch_lds4(const LeafBatch& p, hipStream_t s) {
+  const int64_t tiles_m = (p.m + 127) / 128;
+  const int64_t tiles_n = (((p.n + 63) / 64) * 64 + 63) / 64;
+  const int64_t blocks = ((tiles_m + 1) / 2) * ((tiles_n + 1) / 2) * p.batch;
+  if (blocks == 0) return hipSuccess;
+  if (!grid_fits(blocks, 256)) return kGridTooLarge;
+  const int aligned = ((reinterpret_cast<uintptr_t>(p.A) | reinterpret_cast<uintptr_t>(p.BT)) & 15) == 0 &&
+                      ((p.lda | p.ldbt | p.strideA | p.strideB) & 1) == 0;
+  hipLaunchKernelGGL((leaf_mfma_lds4_kernel<SEMI, FMT, FMT == mfma::FMT_I8>), dim3((unsigned)blocks),
+                     dim3(256), 0, s, p, tiles_m, tiles_n, aligned);
+  return hipGetLastError();
+}
+
 // DEEP: int8 leaves of the recursion's lengths (k = 2048 or 4096 bits, 16-byte
 // aligned) run a fully unrolled 3-deep load pipeline (with the 32-bit operand
 // expansion: the wide one measured no faster there and spills in its prologue).  CHUNKED: aligned int8 leaves
@@ -94,6 +124,7 @@ template <int SEMI, int FMT>
 hipError_t launch_semi(const LeafBatch& p, int tile, hipStream_t s) {
   switch (tile) {
     case MFMA_LDS_256x256: return launch_leaf_mfma_lds(SEMI, FMT, p, s);
+    case MFMA_LDS4_256x128: return launch_lds4<SEMI, FMT>(p, s);
     case MFMA_DEEP_128x64: return launch_t<SEMI, 4, 2, FMT, true>(p, s);
     case MFMA_CHUNK_64x128: return launch_t<SEMI, 2, 4, FMT, false, true>(p, s);
     case MFMA_64x64: return launch_t<SEMI, 2, 2, FMT>(p, s);
@@ -112,6 +143,7 @@ int leaf_mfma_tile_rows(int tile) {
     case MFMA_CHUNK_64x128: return 64;
     case MFMA_64x32: return 64;
     case MFMA_LDS_256x256: return 256;
+    case MFMA_LDS4_256x128: return 256;
     default: return 128;
   }
 }
@@ -123,6 +155,7 @@ int leaf_mfma_tile_cols(int tile) {
     case MFMA_CHUNK_64x128: return 128;
     case MFMA_64x32: return 32;
     case MFMA_LDS_256x256: return 256;
+    case MFMA_LDS4_256x128: return 128;
     default: return 64;
   }
 }

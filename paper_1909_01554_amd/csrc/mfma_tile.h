@@ -344,5 +344,127 @@ tail:
   epilogue<SEMI, RA, RB, FMT>(acc, Cm, ldc, m, n, tm, tn, accumulate, semiring);
 }
 
+// A workgroup item of 2 x 2 wave tiles of 128 x 64 (256 rows of A, 128 rows of B^T,
+// item coordinates (im, in)) with its operand rows staged through LDS: per stage of 8
+// words of k the four waves load those 384 rows once, with 16-byte coalesced loads,
+// into LDS (rows padded to 80 bytes so the lanes of one 16-byte LDS read hit distinct
+// banks), and every wave reads its own rows from there, so each operand row is fetched
+// from L2 once per workgroup instead of once per wave that uses it.  The next stage is
+// loaded into registers while the current one computes.  Words past the end of k read
+// as zero; whole 4-word groups past it are skipped.  All four waves (w = 0..3) take
+// part in the loads and barriers; waves whose tile lies outside the problem only skip
+// the epilogue.  smem: kLdsItemBytes of LDS.
+constexpr int kLdsKs = 8;                          // words of k per stage
+constexpr int kLdsRowB = 80;                       // padded LDS row (64 data bytes + 16)
+constexpr int kLdsRows = 256 + 128;                // A rows, then B^T rows
+constexpr int kLdsPanel = kLdsRows * kLdsRowB;     // bytes per stage buffer
+constexpr int kLdsChunks = kLdsRows * 4 / 256;     // 16-byte chunks per thread per stage
+constexpr int kLdsItemBytes = 2 * kLdsPanel;
+
+template <int SEMI, int FMT, bool WIDE>
+__device__ __forceinline__ void lds_item(const uint64_t* Ap, int64_t lda, const uint64_t* BTp,
+                                         int64_t ldbt, uint64_t* C, int64_t ldc, int64_t m,
+                                         int64_t k, int64_t n, int64_t im, int64_t in,
+                                         int64_t tiles_m, int64_t tiles_n, bool aligned,
+                                         int accumulate, int semiring, int w,
+                                         unsigned char* smem) {
+  constexpr int RA = 4, RB = 2;
+  const int tid = threadIdx.x, lane = tid & 63, half = lane >> 5, li = lane & 31;
+  const int64_t row0 = im * 256, col0 = in * 128;
+  const gq_ptr A = (gq_ptr)Ap;
+  const gq_ptr BT = (gq_ptr)BTp;
+  const int64_t kw = (k + 63) >> 6;
+  // staging: chunk q = tid + 256 i covers row q >> 2, words 2 (q & 3) .. + 1 of a stage
+  gq_ptr src[kLdsChunks];
+  int soff[kLdsChunks], spart[kLdsChunks];
+#pragma unroll
+  for (int i = 0; i < kLdsChunks; ++i) {
+    const int q = tid + 256 * i;
+    const int r = q >> 2, part = q & 3;
+    spart[i] = part;
+    if (r < 256) {
+      int64_t g = row0 + r;
+      g = g < m ? g : m - 1;
+      src[i] = A + g * lda + 2 * part;
+    } else {
+      int64_t g = col0 + (r - 256);
+      g = g < n ? g : n - 1;
+      src[i] = BT + g * ldbt + 2 * part;
+    }
+    soff[i] = r * kLdsRowB + part * 16;
+  }
+  uint64_t stage[kLdsChunks][2];
+  auto load = [&](int64_t w0) {
+#pragma unroll
+    for (int i = 0; i < kLdsChunks; ++i) {
+      const int64_t wd = w0 + 2 * spart[i];
+      if (aligned && wd + 1 < kw) {
+        const ulonglong2 v = *reinterpret_cast<const ulonglong2*>((const uint64_t*)(src[i] + w0));
+        stage[i][0] = v.x;
+        stage[i][1] = v.y;
+      } else {
+        stage[i][0] = wd < kw ? src[i][w0] : 0ull;
+        stage[i][1] = wd + 1 < kw ? src[i][w0 + 1] : 0ull;
+      }
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < kLdsChunks; ++i) {
+      ulonglong2 v;
+      v.x = stage[i][0];
+      v.y = stage[i][1];
+      *reinterpret_cast<ulonglong2*>(smem + buf * kLdsPanel + soff[i]) = v;
+    }
+  };
+  using AccV = typename Acc<FMT>::type;
+  AccV acc[RA][RB];
+#pragma unroll
+  for (int f = 0; f < RA; ++f)
+#pragma unroll
+    for (int g = 0; g < RB; ++g) acc[f][g] = AccV{};
+  const int wy = w >> 1, wx = w & 1;
+  int aoff[RA], boff[RB];
+#pragma unroll
+  for (int f = 0; f < RA; ++f) aoff[f] = (wy * 128 + 32 * f + li) * kLdsRowB + 16 * half;
+#pragma unroll
+  for (int g = 0; g < RB; ++g) boff[g] = (256 + wx * 64 + 32 * g + li) * kLdsRowB + 16 * half;
+
+  const int64_t stages = (kw + kLdsKs - 1) / kLdsKs;
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int64_t st = 0; st < stages; ++st) {
+    const int cur = (int)(st & 1);
+    if (st + 1 < stages) load((st + 1) * kLdsKs);
+    const unsigned char* base = smem + cur * kLdsPanel;
+    // two groups of 4 words per stage: lane half h takes words 4s + 2h and 4s + 2h + 1
+#pragma unroll
+    for (int s2 = 0; s2 < kLdsKs / 4; ++s2) {
+      if (st * kLdsKs + 4 * s2 >= kw) break;  // uniform: only zero words are left
+      uint64_t xa[2][RA], xb[2][RB];
+#pragma unroll
+      for (int f = 0; f < RA; ++f) {
+        const ulonglong2 v = *reinterpret_cast<const ulonglong2*>(base + aoff[f] + 32 * s2);
+        xa[0][f] = v.x;
+        xa[1][f] = v.y;
+      }
+#pragma unroll
+      for (int g = 0; g < RB; ++g) {
+        const ulonglong2 v = *reinterpret_cast<const ulonglong2*>(base + boff[g] + 32 * s2);
+        xb[0][g] = v.x;
+        xb[1][g] = v.y;
+      }
+      mfma_word<SEMI, RA, RB, FMT, WIDE>(xa[0], xb[0], acc);
+      mfma_word<SEMI, RA, RB, FMT, WIDE>(xa[1], xb[1], acc);
+    }
+    if (st + 1 < stages) store(cur ^ 1);
+    __syncthreads();
+  }
+  const int64_t tm = 2 * im + wy, tn = 2 * in + wx;
+  if (tm < tiles_m && tn < tiles_n)
+    epilogue<SEMI, RA, RB, FMT>(acc, C, ldc, m, n, tm, tn, accumulate, semiring);
+}
+
 }  // namespace mfma
 }  // namespace bmm

@@ -12,9 +12,10 @@ pytestmark = pytest.mark.gpu
 SEMIRINGS = [("gf2", oracle.GF2), ("bool", oracle.BOOLEAN)]
 LEAVES = [("valu", 1, 1), ("mfma128x64", 2, 1), ("mfma64x64", 2, 2), ("mfma64x128", 2, 3),
           ("mfma64x32", 2, 4), ("mfma_lds256", 2, 5), ("mfma_deep128x64", 2, 6),
-          ("mfma_chunk64x128", 2, 7),
+          ("mfma_chunk64x128", 2, 7), ("mfma_lds4_256x128", 2, 8),
           ("f4_128x64", 3, 1), ("f4_64x64", 3, 2), ("f4_64x128", 3, 3), ("f4_64x32", 3, 4),
-          ("f4_lds256", 3, 5), ("f4_deep128x64", 3, 6), ("f4_chunk64x128", 3, 7)]
+          ("f4_lds256", 3, 5), ("f4_deep128x64", 3, 6), ("f4_chunk64x128", 3, 7),
+          ("f4_lds4_256x128", 3, 8)]
 
 
 @pytest.fixture(scope="module")
