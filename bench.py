@@ -267,7 +267,14 @@ def run_batched(args, torch, np, bmm, bmmgen):
             cands[f"{lname}_{tname}"] = round(e0.elapsed_time(e1) / 1e3, 5)
             pl.destroy()
     leaf, tile, _ = bmm.bmm_autotune_batched(probs)
-    log(f"[bench] batched candidates {cands}; autotuner: leaf {leaf} tile {tile}")
+    # the per-size-class choices the autotuner kept (only where the mix was faster)
+    import tempfile
+    with tempfile.NamedTemporaryFile("r", suffix=".txt") as tf:
+        bmm.bmm_autotune_save(tf.name)
+        per_class = [ln.split()[3:] for ln in open(tf.name)
+                     if ln.startswith(f"batched_class {args.problems} ")]
+    log(f"[bench] batched candidates {cands}; autotuner: leaf {leaf} tile {tile}, "
+        f"per-class choices {per_class}")
     plan = bmm.BatchedPlan(probs)  # AUTO options: the autotuner's choice
     s = torch.cuda.Stream()
     g = torch.cuda.CUDAGraph()
@@ -322,7 +329,9 @@ def run_batched(args, torch, np, bmm, bmmgen):
         "one_launch_per_product_pbops": round(bops / t_loop / 1e15, 4),
         "speedup": round(t_loop / t_graph, 3), "verified_16_problems": ok,
         "autotuned": {"leaf": {2: "int8", 3: "fp4"}[leaf],
-                      "tile": {1: "128x64", 2: "64x64", 3: "64x128", 4: "128x64lds"}[tile]},
+                      "tile": {1: "128x64", 2: "64x64", 3: "64x128", 4: "128x64lds"}[tile],
+                      "per_k_class": {f"class{c}": {"leaf": {1: "valu", 2: "int8", 3: "fp4"}[
+                          int(lf)], "tile": int(t)} for c, lf, t in per_class}},
         "candidates_s": cands,
         "frac_of_peak": round(bops / t_graph / 1e12 / (PEAK_MFMA_F4_TOPS if leaf == 3
                                                         else PEAK_MFMA_I8_TOPS), 4)}), flush=True)

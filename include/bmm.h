@@ -225,20 +225,27 @@ int bmm_batched_plan_create(const bmm_problem* problems, int64_t count,
                             const bmm_options* opt, void** plan_out);
 int bmm_batched_plan_launch(void* plan, void* hip_stream);
 void bmm_batched_plan_destroy(void* plan);
-/* Leaf and tile of a batched plan: opt->leaf BMM_LEAF_MFMA_I8 or BMM_LEAF_MFMA_F4
- * (BMM_LEAF_VALU: BMM_E_UNSUPPORTED), opt->tile 1 (128 x 64 output tile per wave),
+/* Leaf and tile of a batched plan, per problem: opt->leaf and opt->tile where given
+ * (BMM_LEAF_MFMA_I8 or BMM_LEAF_MFMA_F4 with tile 1 (128 x 64 output tile per wave),
  * 2 (64 x 64), 3 (64 x 128) or 4 (128 x 64 with the workgroup's operand rows staged
- * through LDS and shared by its four waves); 0 / AUTO take the autotuner's record for plans of the same
- * problem count and total work (to a factor of two), else int8 with 64 x 64.  The
- * persistent grid (workgroups per CU) comes from the same record, else 4. */
+ * through LDS and shared by its four waves); BMM_LEAF_VALU: the VALU leaf, one launch
+ * per problem); 0 / AUTO take the autotuner's record for plans of the same problem
+ * count and total work (to a factor of two): its choice per size class of k
+ * (k < 1024, < 4096, larger) where it recorded one, else its single choice, else int8
+ * with tile 4.  Problems with the same matrix-core choice share one persistent launch
+ * (workgroups per CU from the same record, else 4); a plan's launch enqueues the VALU
+ * products, then each persistent group. */
 
 /* Autotuner for batched plans (the paper's empirical parameter choice,
  * section 3.17, applied to the persistent launch): times one launch of the plan
- * for every leaf kind (int8, fp4), tile (1, 2, 3, 4) and persistent grid (2 or 4
- * workgroups per CU) on the default stream, records the fastest for later
- * plans with AUTO options (saved by bmm_autotune_save), and returns its leaf
- * and tile.  Problems as for bmm_batched_plan_create; their outputs are
- * overwritten.  Synchronous; allocates (plans). */
+ * for every matrix-core leaf kind (int8, fp4), tile (1, 2, 3, 4) and persistent grid
+ * (2 or 4 workgroups per CU) on the default stream; then, per size class of k, every
+ * leaf kind (VALU included) and tile on that class's problems alone, and keeps the
+ * per-class choices if the plan they give is faster than the single best choice.
+ * Records the result for later plans with AUTO options (saved by bmm_autotune_save)
+ * and returns the single best leaf and tile (*seconds_out: the faster of the two
+ * plans).  Problems as for bmm_batched_plan_create; their outputs are overwritten.
+ * Synchronous; allocates (plans). */
 int bmm_autotune_batched(const bmm_problem* problems, int64_t count, int* leaf_out,
                          int* tile_out, double* seconds_out);
 

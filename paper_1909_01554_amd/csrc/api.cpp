@@ -139,8 +139,11 @@ std::map<TuneKey, TuneVal> g_tune;
 std::map<std::tuple<int64_t, int64_t, int64_t>, std::tuple<int, int, int>> g_depth;
 // Batched plans: (problem count, floor(log2(total ops))) -> (leaf, tile, workgroups per CU).
 std::map<std::pair<int64_t, int>, std::tuple<int, int, int>> g_batched;
-// Bumped whenever g_batched changes, so cached batched plans built from older records
-// are rebuilt.
+// Per size class of k within such plans: (count, floor(log2(total ops)), class) ->
+// (leaf, tile), where the autotuner found a mix of choices faster than one choice.
+std::map<std::tuple<int64_t, int, int>, std::pair<int, int>> g_bclass;
+// Bumped whenever g_batched or g_bclass changes, so cached batched plans built from older
+// records are rebuilt.
 std::atomic<uint64_t> g_batched_gen{0};
 
 int ops_bucket(double ops) {
@@ -699,6 +702,29 @@ void batched_tune_set(int64_t count, double ops, int leaf, int tile, int wg_per_
 
 uint64_t batched_tune_generation() { return g_batched_gen.load(); }
 
+bool batched_class_tuned(int64_t count, double ops, int kclass, int* leaf, int* tile) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  auto it = g_bclass.find({count, ops_bucket(ops), kclass});
+  if (it == g_bclass.end()) return false;
+  std::tie(*leaf, *tile) = it->second;
+  return true;
+}
+
+void batched_class_set(int64_t count, double ops, int kclass, int leaf, int tile) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  g_bclass[{count, ops_bucket(ops), kclass}] = {leaf, tile};
+  ++g_batched_gen;
+}
+
+void batched_class_clear(int64_t count, double ops) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  const int b = ops_bucket(ops);
+  for (auto it = g_bclass.begin(); it != g_bclass.end();)
+    it = (std::get<0>(it->first) == count && std::get<1>(it->first) == b) ? g_bclass.erase(it)
+                                                                           : std::next(it);
+  ++g_batched_gen;
+}
+
 void choose_leaf(int semiring, int64_t m, int64_t k, int64_t n, int64_t batch,
                  const bmm_options& o, int* leaf, int* tile) {
   pick_leaf(semiring, m, k, n, batch, o, leaf, tile);
@@ -1034,7 +1060,8 @@ int bmm_autotune_save(const char* path) {
   f << "# bmm autotune table\n"
        "# leaf semiring m k n batch_bucket best_leaf tile_valu tile_mfma_i8 tile_mfma_f4\n"
        "# depth m k n depth depth_serial shift\n"
-       "# batched count log2_ops leaf tile workgroups_per_cu\n";
+       "# batched count log2_ops leaf tile workgroups_per_cu\n"
+       "# batched_class count log2_ops k_class leaf tile\n";
   for (auto& [key, val] : g_tune)
     f << "leaf " << key.semiring << ' ' << key.m << ' ' << key.k << ' ' << key.n << ' '
       << key.batch << ' ' << val.best_leaf << ' ' << val.tile[1] << ' ' << val.tile[2] << ' '
@@ -1045,6 +1072,9 @@ int bmm_autotune_save(const char* path) {
   for (auto& [key, val] : g_batched)
     f << "batched " << key.first << ' ' << key.second << ' ' << std::get<0>(val) << ' '
       << std::get<1>(val) << ' ' << std::get<2>(val) << '\n';
+  for (auto& [key, val] : g_bclass)
+    f << "batched_class " << std::get<0>(key) << ' ' << std::get<1>(key) << ' '
+      << std::get<2>(key) << ' ' << val.first << ' ' << val.second << '\n';
   return f ? BMM_OK : fail(BMM_E_INVAL, "write failed: %s", path);
 }
 
@@ -1077,6 +1107,14 @@ int bmm_autotune_load(const char* path) {
         return fail(BMM_E_INVAL, "bad depth line: %s", line.c_str());
       std::lock_guard<std::mutex> lock(g_mu);
       g_depth[{m, k, n}] = {d, ds, sh};
+    } else if (sscanf(line.c_str(), "batched_class %lld %d %d %d %d", &m, &d, &ds, &leaf, &t1) ==
+               5) {
+      if (m <= 0 || d < 0 || ds < 0 || ds > 2 || leaf < BMM_LEAF_VALU || leaf > BMM_LEAF_MFMA_F4 ||
+          t1 < 1 || t1 > 4)
+        return fail(BMM_E_INVAL, "bad batched_class line: %s", line.c_str());
+      std::lock_guard<std::mutex> lock(g_mu);
+      g_bclass[{m, d, ds}] = {leaf, t1};
+      ++g_batched_gen;
     } else if (sscanf(line.c_str(), "batched %lld %d %d %d %d", &m, &d, &leaf, &t1, &t2) >= 4) {
       if (sscanf(line.c_str(), "batched %lld %d %d %d %d", &m, &d, &leaf, &t1, &t2) == 4) t2 = 4;
       if (m <= 0 || d < 0 || (leaf != BMM_LEAF_MFMA_I8 && leaf != BMM_LEAF_MFMA_F4) ||
@@ -1130,6 +1168,7 @@ void bmm_finalize(void) {
   g_tune.clear();
   g_depth.clear();
   g_batched.clear();
+  g_bclass.clear();
   ++g_batched_gen;
 }
 

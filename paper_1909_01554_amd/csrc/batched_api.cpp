@@ -19,6 +19,14 @@ namespace {
 
 #define bfail bmm::set_error
 
+#define BMM_BTRY(expr)              \
+  do {                              \
+    int _rc = (expr);               \
+    if (_rc != BMM_OK) return _rc;  \
+  } while (0)
+
+// One persistent group of a plan: a device problem table, its per-XCD queues and their
+// counters, for problems that share a matrix-core leaf kind and tile.
 struct Plan {
   BatchedDesc* descs = nullptr;  // device
   BatchedSeg* segs = nullptr;    // device: every queue's segments, queue after queue
@@ -28,10 +36,8 @@ struct Plan {
   int grid = 0;
   int device = 0;
   int leaf = BMM_LEAF_MFMA_I8;  // BMM_LEAF_MFMA_I8 or BMM_LEAF_MFMA_F4
-  int tile = 2;                 // 1: 128 x 64 per wave, 2: 64 x 64, 3: 64 x 128
-  // Marks the end of the last launch enqueued outside stream capture; the next launch
-  // (on any stream) waits for it, so launches that share the queue counters never overlap.
-  hipEvent_t done = nullptr;
+  int tile = 4;                 // 1: 128 x 64 per wave, 2: 64 x 64, 3: 64 x 128,
+                                // 4: 128 x 64 with LDS-shared operand rows
 };
 
 bool capturing(hipStream_t s) {
@@ -39,46 +45,14 @@ bool capturing(hipStream_t s) {
   return hipStreamIsCapturing(s, &st) == hipSuccess && st != hipStreamCaptureStatusNone;
 }
 
-// Launch a plan's kernels (counter reset + persistent kernel) on s.  Outside stream
-// capture the launch is ordered after the plan's previous one by its event.
-int plan_enqueue(Plan* P, hipStream_t s) {
-  if (P->count == 0) return BMM_OK;
-  const bool cap = capturing(s);
-  if (!cap) {
-    if (!P->done && hipEventCreateWithFlags(&P->done, hipEventDisableTiming) != hipSuccess)
-      return bfail(BMM_E_DEVICE, "plan event: %s", hipGetErrorString(hipGetLastError()));
-    if (hipStreamWaitEvent(s, P->done, 0) != hipSuccess)
-      return bfail(BMM_E_DEVICE, "plan order: %s", hipGetErrorString(hipGetLastError()));
-  }
-  hipError_t e = launch_batched_persistent(
-      P->descs, P->segs, P->queues, P->counters, P->grid, P->tile,
-      P->leaf == BMM_LEAF_MFMA_F4 ? 1 : 0, s);
-  if (e != hipSuccess) return bfail(BMM_E_DEVICE, "batched launch: %s", hipGetErrorString(e));
-  if (!cap && hipEventRecord(P->done, s) != hipSuccess)
-    return bfail(BMM_E_DEVICE, "plan event: %s", hipGetErrorString(hipGetLastError()));
-  return BMM_OK;
-}
-
+// Free a group's device memory; the caller has made sure no launch of it still runs.
 void plan_free(Plan* P) {
-  if (P->descs || P->counters || P->done) {
-    int cur = 0;
-    (void)hipGetDevice(&cur);
-    (void)hipSetDevice(P->device);
-    if (P->done) {
-      (void)hipEventSynchronize(P->done);
-      (void)hipEventDestroy(P->done);
-    } else {
-      (void)hipDeviceSynchronize();
-    }
-    (void)hipFree(P->descs);
-    (void)hipFree(P->segs);
-    (void)hipFree(P->counters);
-    (void)hipSetDevice(cur);
-  }
+  (void)hipFree(P->descs);
+  (void)hipFree(P->segs);
+  (void)hipFree(P->counters);
   P->descs = nullptr;
   P->segs = nullptr;
   P->counters = nullptr;
-  P->done = nullptr;
 }
 
 int validate_problem(const bmm_problem& p, int64_t i) {
@@ -99,42 +73,24 @@ int validate_problem(const bmm_problem& p, int64_t i) {
   return BMM_OK;
 }
 
-// wg_per_cu > 0 fixes the persistent grid (workgroups per CU); 0 takes the record.
-int build_plan(const bmm_problem* problems, int64_t count, const bmm_options* opt,
-               int wg_per_cu, Plan* out) {
-  if (count < 0 || (count > 0 && !problems)) return bfail(BMM_E_INVAL, "bad problem list");
+// One persistent group: the problems `idx` of the table (validated, B^T given), all
+// with the same matrix-core leaf kind and tile, on a grid of wg_per_cu workgroups per CU.
+int build_plan(const bmm_problem* problems, const std::vector<int64_t>& idx, int leaf,
+               int tile, int wg_per_cu, Plan* out) {
   std::vector<int64_t> order;
-  double ops = 0;
   int64_t kmax = 0;
-  for (int64_t i = 0; i < count; ++i) {
-    int rc = validate_problem(problems[i], i);
-    if (rc != BMM_OK) return rc;
-    if (!problems[i].b_transposed)
-      return bfail(BMM_E_INVAL, "problem %ld: plans need B passed transposed", (long)i);
+  for (int64_t i : idx) {
     if (problems[i].m > 0 && problems[i].n > 0) order.push_back(i);
-    ops += 2.0 * problems[i].m * problems[i].k * problems[i].n;
     kmax = std::max(kmax, problems[i].k);
   }
-  // leaf kind and tile: explicit options, else the autotuner's record for plans of this
-  // count and total work, else int8 with 64 x 64 tiles
-  int leaf = opt ? opt->leaf : BMM_LEAF_AUTO;
-  int tile = opt ? opt->tile : 0;
-  int tl = 0, tt = 0, tw = 0;
-  if (batched_tuned(count, ops, &tl, &tt, &tw)) {
-    if (leaf == BMM_LEAF_AUTO) leaf = tl;
-    if (tile <= 0) tile = tt;
-    if (wg_per_cu <= 0) wg_per_cu = tw;
-  }
-  if (wg_per_cu <= 0) wg_per_cu = 4;
-  if (leaf == BMM_LEAF_AUTO) leaf = BMM_LEAF_MFMA_I8;
-  if (tile <= 0) tile = 2;
   if (leaf != BMM_LEAF_MFMA_I8 && leaf != BMM_LEAF_MFMA_F4)
-    return bfail(BMM_E_UNSUPPORTED, "batched plans run the int8 or fp4 matrix-core leaf");
+    return bfail(BMM_E_UNSUPPORTED, "persistent groups run the int8 or fp4 matrix-core leaf");
   if (tile < 1 || tile > 4) return bfail(BMM_E_INVAL, "batched tile must be 1, 2, 3 or 4");
   if (leaf == BMM_LEAF_MFMA_F4 && kmax >= ((int64_t)1 << 24))
     return bfail(BMM_E_UNSUPPORTED, "the fp4 leaf counts exactly only for k < 2^24");
   if (kmax >= ((int64_t)1 << 31))
     return bfail(BMM_E_UNSUPPORTED, "the int8 leaf counts exactly only for k < 2^31");
+  if (wg_per_cu <= 0) wg_per_cu = 4;
   // longest k first, so the queues drain with short items at the end
   std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
     return problems[a].k > problems[b].k;
@@ -228,23 +184,143 @@ int build_plan(const bmm_problem* problems, int64_t count, const bmm_options* op
   return BMM_OK;
 }
 
-#define BMM_BTRY(expr)              \
-  do {                              \
-    int _rc = (expr);               \
-    if (_rc != BMM_OK) return _rc;  \
-  } while (0)
+// Size class of a problem for per-class leaf choices (k < 1024, < 4096, else).
+int k_class(int64_t k) { return k < 1024 ? 0 : (k < 4096 ? 1 : 2); }
+constexpr int kKClasses = 3;
+
+// A batched plan: the problems grouped by the leaf kind and tile chosen for each, one
+// persistent launch per matrix-core group and one VALU leaf launch per VALU problem,
+// enqueued in that order.  `done` orders launches of one plan (see plan_enqueue).
+struct PlanSet {
+  std::vector<Plan> groups;
+  std::vector<std::pair<int, LeafBatch>> valu;  // (semiring, product)
+  int device = 0;
+  hipEvent_t done = nullptr;
+};
+
+// Choices per problem: opt's leaf and tile where given; else the autotuner's per-class
+// record for plans of this count and total work, else its plan-wide record, else int8
+// with the LDS-shared 128 x 64 item (tile 4).  force_* (>= 0) override everything.
+int build_set(const bmm_problem* problems, int64_t count, const bmm_options* opt,
+              int force_leaf, int force_tile, int force_wpc, PlanSet* out) {
+  if (count < 0 || (count > 0 && !problems)) return bfail(BMM_E_INVAL, "bad problem list");
+  double ops = 0;
+  for (int64_t i = 0; i < count; ++i) {
+    int rc = validate_problem(problems[i], i);
+    if (rc != BMM_OK) return rc;
+    if (!problems[i].b_transposed)
+      return bfail(BMM_E_INVAL, "problem %ld: plans need B passed transposed", (long)i);
+    ops += 2.0 * problems[i].m * problems[i].k * problems[i].n;
+  }
+  const int oleaf = opt ? opt->leaf : BMM_LEAF_AUTO;
+  const int otile = opt ? opt->tile : 0;
+  if (oleaf < BMM_LEAF_AUTO || oleaf > BMM_LEAF_MFMA_F4)
+    return bfail(BMM_E_INVAL, "unknown leaf %d", oleaf);
+  int pl = 0, pt = 0, pw = 0;
+  const bool plan_rec = batched_tuned(count, ops, &pl, &pt, &pw);
+  int wpc = force_wpc > 0 ? force_wpc : (plan_rec ? pw : 4);
+  // (leaf, tile) -> problem indices, in table order
+  std::vector<std::pair<std::pair<int, int>, std::vector<int64_t>>> groups;
+  PlanSet S;
+  for (int64_t i = 0; i < count; ++i) {
+    const bmm_problem& p = problems[i];
+    int leaf = oleaf, tile = otile, cl = 0, ct = 0;
+    const bool class_rec = batched_class_tuned(count, ops, k_class(p.k), &cl, &ct);
+    if (leaf == BMM_LEAF_AUTO) leaf = class_rec ? cl : (plan_rec ? pl : BMM_LEAF_MFMA_I8);
+    if (tile <= 0) tile = class_rec && cl == leaf ? ct : (plan_rec && pl == leaf ? pt : 4);
+    if (force_leaf > 0) leaf = force_leaf;
+    if (force_tile > 0) tile = force_tile;
+    if (leaf == BMM_LEAF_VALU) {
+      if (p.m > 0 && p.n > 0)
+        S.valu.push_back({p.semiring, LeafBatch{p.A, p.lda, 0, p.B, p.ldb, 0, p.C, p.ldc, 0,
+                                                p.m, p.k, p.n, 1, 0}});
+      continue;
+    }
+    auto it = std::find_if(groups.begin(), groups.end(),
+                           [&](const auto& g) { return g.first == std::make_pair(leaf, tile); });
+    if (it == groups.end()) {
+      groups.push_back({{leaf, tile}, {}});
+      it = groups.end() - 1;
+    }
+    it->second.push_back(i);
+  }
+  if (hipGetDevice(&S.device) != hipSuccess) return bfail(BMM_E_DEVICE, "hipGetDevice");
+  for (auto& g : groups) {
+    S.groups.emplace_back();
+    int rc = build_plan(problems, g.second, g.first.first, g.first.second, wpc, &S.groups.back());
+    if (rc != BMM_OK) {
+      S.groups.pop_back();
+      for (Plan& P : S.groups) plan_free(&P);
+      return rc;
+    }
+  }
+  *out = std::move(S);
+  return BMM_OK;
+}
+
+// The set's kernels on s: VALU products (k = 0: C zeroed), then every persistent group.
+int set_kernels(const PlanSet* S, hipStream_t s) {
+  for (const auto& [sr, lb] : S->valu) {
+    hipError_t e = lb.k == 0 ? launch_zero(lb.C, lb.ldc, lb.m, (lb.n + 63) / 64, s)
+                             : launch_leaf_valu(sr, lb, 0, s);
+    if (e != hipSuccess) return bfail(BMM_E_DEVICE, "batched VALU leaf: %s", hipGetErrorString(e));
+  }
+  for (const Plan& P : S->groups) {
+    if (P.count == 0) continue;
+    hipError_t e = launch_batched_persistent(P.descs, P.segs, P.queues, P.counters, P.grid,
+                                             P.tile, P.leaf == BMM_LEAF_MFMA_F4 ? 1 : 0, s);
+    if (e != hipSuccess) return bfail(BMM_E_DEVICE, "batched launch: %s", hipGetErrorString(e));
+  }
+  return BMM_OK;
+}
+
+// Launch a set on s.  Outside stream capture the launch is ordered after the set's
+// previous one by its event (launches share the groups' queue counters).
+int set_enqueue(PlanSet* S, hipStream_t s) {
+  const bool cap = capturing(s);
+  if (!cap) {
+    if (!S->done && hipEventCreateWithFlags(&S->done, hipEventDisableTiming) != hipSuccess)
+      return bfail(BMM_E_DEVICE, "plan event: %s", hipGetErrorString(hipGetLastError()));
+    if (hipStreamWaitEvent(s, S->done, 0) != hipSuccess)
+      return bfail(BMM_E_DEVICE, "plan order: %s", hipGetErrorString(hipGetLastError()));
+  }
+  BMM_BTRY(set_kernels(S, s));
+  if (!cap && hipEventRecord(S->done, s) != hipSuccess)
+    return bfail(BMM_E_DEVICE, "plan event: %s", hipGetErrorString(hipGetLastError()));
+  return BMM_OK;
+}
+
+// Free a set once its launches have finished: the last one ordered by its event, or,
+// if it was only ever launched inside stream capture, whatever the device still runs.
+void set_free(PlanSet* S) {
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(S->device);
+  if (S->done) {
+    (void)hipEventSynchronize(S->done);
+    (void)hipEventDestroy(S->done);
+    S->done = nullptr;
+  } else if (!S->groups.empty()) {
+    (void)hipDeviceSynchronize();
+  }
+  for (Plan& P : S->groups) plan_free(&P);
+  (void)hipSetDevice(cur);
+  S->groups.clear();
+  S->valu.clear();
+}
 
 // Library-owned plans of bmm_batched, keyed by the problem table (pointers, sizes,
 // pitches, semirings), the leaf and tile options and the device.  An entry owns the
 // device problem table, a staging buffer for right operands not given transposed,
-// and a HIP graph of its launch sequence (the transposes into staging, the counter
-// reset and the persistent kernel), captured on its first call and replayed on the
-// caller's stream by later calls.  Launches of one entry are ordered by its event.
+// and a HIP graph of its launch sequence (the transposes into staging, then the plan's
+// kernels: VALU products, and per persistent group the counter reset and the persistent
+// kernel), captured on its first call and replayed on the caller's stream by later
+// calls.  Launches of one entry are ordered by its event.
 struct BatchedEntry {
   std::vector<bmm_problem> key;
   int leaf = 0, tile = 0, device = 0;
   uint64_t tune_gen = 0;  // the batched tuning records the plan was built from
-  Plan plan;
+  PlanSet plan;
   std::vector<bmm_problem> staged;  // the problems as the plan sees them (B^T everywhere)
   uint64_t* stage = nullptr;
   hipGraph_t graph = nullptr;
@@ -276,12 +352,7 @@ struct BatchedEntry {
                                       p.n, 1, s);
       if (e != hipSuccess) return bfail(BMM_E_DEVICE, "transpose: %s", hipGetErrorString(e));
     }
-    if (plan.count == 0) return BMM_OK;
-    hipError_t e = launch_batched_persistent(plan.descs, plan.segs, plan.queues, plan.counters,
-                                             plan.grid, plan.tile,
-                                             plan.leaf == BMM_LEAF_MFMA_F4 ? 1 : 0, s);
-    if (e != hipSuccess) return bfail(BMM_E_DEVICE, "batched launch: %s", hipGetErrorString(e));
-    return BMM_OK;
+    return set_kernels(&plan, s);
   }
 
   int build(const bmm_problem* p, int64_t count, const bmm_options* opt, int lf, int tl,
@@ -311,7 +382,7 @@ struct BatchedEntry {
       }
       q.b_transposed = 1;
     }
-    BMM_BTRY(build_plan(staged.data(), count, opt, 0, &plan));
+    BMM_BTRY(build_set(staged.data(), count, opt, 0, 0, 0, &plan));
     if (hipEventCreateWithFlags(&done, hipEventDisableTiming) != hipSuccess)
       return bfail(BMM_E_DEVICE, "batched event: %s", hipGetErrorString(hipGetLastError()));
     // capture the sequence once; if this runtime cannot, launches enqueue it directly
@@ -357,7 +428,7 @@ struct BatchedEntry {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
     if (done) (void)hipEventDestroy(done);
-    plan_free(&plan);
+    for (Plan& P : plan.groups) plan_free(&P);  // the entry's event covered its launches
     (void)hipFree(stage);
     (void)hipSetDevice(cur);
   }
@@ -375,27 +446,59 @@ extern "C" {
 int bmm_batched_plan_create(const bmm_problem* problems, int64_t count,
                             const bmm_options* opt, void** plan_out) {
   if (!plan_out) return bfail(BMM_E_INVAL, "null plan_out");
-  Plan* P = new Plan();
-  int rc = build_plan(problems, count, opt, 0, P);
+  PlanSet* S = new PlanSet();
+  int rc = build_set(problems, count, opt, 0, 0, 0, S);
   if (rc != BMM_OK) {
-    delete P;
+    delete S;
     return rc;
   }
-  *plan_out = P;
+  *plan_out = S;
   return BMM_OK;
 }
 
 int bmm_batched_plan_launch(void* plan, void* hip_stream) {
   if (!plan) return bfail(BMM_E_INVAL, "null plan");
-  return plan_enqueue(static_cast<Plan*>(plan), (hipStream_t)hip_stream);
+  return set_enqueue(static_cast<PlanSet*>(plan), (hipStream_t)hip_stream);
 }
 
 void bmm_batched_plan_destroy(void* plan) {
   if (!plan) return;
-  Plan* P = static_cast<Plan*>(plan);
-  plan_free(P);
-  delete P;
+  PlanSet* S = static_cast<PlanSet*>(plan);
+  set_free(S);
+  delete S;
 }
+
+}  // extern "C"
+
+namespace {
+
+// Seconds of one launch of the set built with these forced choices (after a warm-up),
+// or a negative value when the choice does not apply (e.g. fp4 with k >= 2^24).
+int time_set(const bmm_problem* problems, int64_t count, int leaf, int tile, int wpc,
+             hipEvent_t e0, hipEvent_t e1, double* secs) {
+  *secs = -1.0;
+  PlanSet S;
+  int rc = build_set(problems, count, nullptr, leaf, tile, wpc, &S);
+  if (rc == BMM_E_UNSUPPORTED) return BMM_OK;
+  BMM_BTRY(rc);
+  rc = set_enqueue(&S, nullptr);  // warm-up
+  if (rc == BMM_OK) {
+    (void)hipEventRecord(e0, nullptr);
+    rc = set_enqueue(&S, nullptr);
+    (void)hipEventRecord(e1, nullptr);
+  }
+  float ms = 0.f;
+  if (rc == BMM_OK && (hipEventSynchronize(e1) != hipSuccess ||
+                       hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+    rc = bfail(BMM_E_DEVICE, "autotune timing: %s", hipGetErrorString(hipGetLastError()));
+  set_free(&S);
+  if (rc == BMM_OK) *secs = ms * 1e-3;
+  return rc;
+}
+
+}  // namespace
+
+extern "C" {
 
 int bmm_autotune_batched(const bmm_problem* problems, int64_t count, int* leaf_out,
                          int* tile_out, double* seconds_out) {
@@ -405,52 +508,78 @@ int bmm_autotune_batched(const bmm_problem* problems, int64_t count, int* leaf_o
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     return bfail(BMM_E_DEVICE, "event create");
+  // 1. one leaf kind and tile for the whole plan, and the persistent grid
   double best = 1e30;
-  int best_leaf = BMM_LEAF_MFMA_I8, best_tile = 2, best_wpc = 4, rc = BMM_OK;
-  for (int leaf : {BMM_LEAF_MFMA_I8, BMM_LEAF_MFMA_F4}) {
-    for (int tile : {1, 2, 3, 4}) {
+  int best_leaf = BMM_LEAF_MFMA_I8, best_tile = 4, best_wpc = 4, rc = BMM_OK;
+  for (int leaf : {BMM_LEAF_MFMA_I8, BMM_LEAF_MFMA_F4})
+    for (int tile : {1, 2, 3, 4})
       for (int wpc : {2, 4}) {
-        bmm_options o;
-        bmm_options_init(&o);
-        o.leaf = leaf;
-        o.tile = tile;
-        Plan* plan = new Plan();
-        rc = build_plan(problems, count, &o, wpc, plan);
-        if (rc == BMM_E_UNSUPPORTED) {  // e.g. fp4 with k >= 2^24: not a candidate
-          delete plan;
-          rc = BMM_OK;
-          continue;
+        double t = 0;
+        if (rc == BMM_OK) rc = time_set(problems, count, leaf, tile, wpc, e0, e1, &t);
+        if (rc == BMM_OK && t >= 0 && t < best) {
+          best = t;
+          best_leaf = leaf;
+          best_tile = tile;
+          best_wpc = wpc;
         }
-        if (rc != BMM_OK) {
-          delete plan;
-          break;
+      }
+  // 2. per size class of k: every leaf kind (VALU included) and tile on that class's
+  // problems alone, then the mix of the classes' choices against the single choice
+  std::vector<std::pair<int, int>> cls(kKClasses, {0, 0});
+  double mixed = -1.0;
+  if (rc == BMM_OK) {
+    std::vector<std::vector<bmm_problem>> members(kKClasses);
+    for (int64_t i = 0; i < count; ++i) members[k_class(problems[i].k)].push_back(problems[i]);
+    for (int c = 0; c < kKClasses && rc == BMM_OK; ++c) {
+      if (members[c].empty()) continue;
+      double cbest = 1e30;
+      cls[c] = {best_leaf, best_tile};
+      std::vector<std::pair<int, int>> cands = {{BMM_LEAF_VALU, 1}};
+      for (int leaf : {BMM_LEAF_MFMA_I8, BMM_LEAF_MFMA_F4})
+        for (int tile : {1, 2, 3, 4}) cands.push_back({leaf, tile});
+      for (auto [leaf, tile] : cands) {
+        double t = 0;
+        rc = time_set(members[c].data(), (int64_t)members[c].size(), leaf, tile, best_wpc, e0,
+                      e1, &t);
+        if (rc != BMM_OK) break;
+        if (t >= 0 && t < cbest) {
+          cbest = t;
+          cls[c] = {leaf, tile};
         }
-        rc = bmm_batched_plan_launch(plan, nullptr);  // warm-up
+      }
+    }
+    if (rc == BMM_OK) {
+      // the mix: record the class choices, time the plan they give
+      for (int c = 0; c < kKClasses; ++c)
+        if (cls[c].first) batched_class_set(count, ops, c, cls[c].first, cls[c].second);
+      batched_tune_set(count, ops, best_leaf, best_tile, best_wpc);
+      PlanSet S;
+      rc = build_set(problems, count, nullptr, 0, 0, best_wpc, &S);
+      if (rc == BMM_OK) {
+        rc = set_enqueue(&S, nullptr);
         if (rc == BMM_OK) {
           (void)hipEventRecord(e0, nullptr);
-          rc = bmm_batched_plan_launch(plan, nullptr);
+          rc = set_enqueue(&S, nullptr);
           (void)hipEventRecord(e1, nullptr);
         }
         float ms = 0.f;
         if (rc == BMM_OK && (hipEventSynchronize(e1) != hipSuccess ||
                              hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
           rc = bfail(BMM_E_DEVICE, "autotune timing: %s", hipGetErrorString(hipGetLastError()));
-        bmm_batched_plan_destroy(plan);
-        if (rc != BMM_OK) break;
-        if (ms * 1e-3 < best) {
-          best = ms * 1e-3;
-          best_leaf = leaf;
-          best_tile = tile;
-          best_wpc = wpc;
-        }
+        set_free(&S);
+        mixed = ms * 1e-3;
       }
-      if (rc != BMM_OK) break;
     }
-    if (rc != BMM_OK) break;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc != BMM_OK) return rc;
+  // keep the per-class choices only where the mix beats the single choice
+  if (!(mixed > 0 && mixed < best)) {
+    batched_class_clear(count, ops);
+  } else {
+    best = mixed;
+  }
   batched_tune_set(count, ops, best_leaf, best_tile, best_wpc);
   if (leaf_out) *leaf_out = best_leaf;
   if (tile_out) *tile_out = best_tile;

@@ -215,6 +215,11 @@ int batched_tile_cols(int tile);
 // power of two (kept with the other autotune tables).
 bool batched_tuned(int64_t count, double ops, int* leaf, int* tile, int* wg_per_cu);
 void batched_tune_set(int64_t count, double ops, int leaf, int tile, int wg_per_cu);
+// Per size class of k (0: k < 1024, 1: < 4096, 2: else) within such plans: the leaf kind
+// (VALU included) and tile the autotuner chose where a mix beat one choice for all.
+bool batched_class_tuned(int64_t count, double ops, int kclass, int* leaf, int* tile);
+void batched_class_set(int64_t count, double ops, int kclass, int leaf, int tile);
+void batched_class_clear(int64_t count, double ops);
 
 }  // namespace bmm
 

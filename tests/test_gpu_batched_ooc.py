@@ -114,9 +114,11 @@ def test_batched_autotune_and_auto_plan(bmm):
     plan.launch()
     check(probs, host)
     plan.destroy()
-    with pytest.raises(bmm.BmmError) as e:
-        bmm.bmm_batched(probs, options=bmm.Options(leaf=1))
-    assert e.value.status == -2  # no VALU batched leaf
+    for pr in probs:
+        pr["C"].fill_(-1)
+    announce("batched VALU leaf")
+    bmm.bmm_batched(probs, options=bmm.Options(leaf=1))  # one VALU launch per problem
+    check(probs, host)
 
 
 def test_batched_plan_graph_replay(bmm):
@@ -324,3 +326,35 @@ def test_host_operands_through_product_calls(bmm, which):
     with pytest.raises(bmm.BmmError) as e:  # no accumulation out of core
         bmm.bmm_gf2(Ah, Bh, Ch, m, k, n, accumulate=True, host_operands=True)
     assert e.value.status == -2
+
+
+def test_batched_plan_mixes_leaves_per_class(bmm, tmp_path):
+    """A plan whose problems take different leaf kinds and tiles by size class of k
+    (records loaded from a table): VALU launches for the short ones, an int8 and an fp4
+    persistent group for the others, all exact."""
+    probs, host = make_problems(30, 515, maxdim=6000)
+    ops = float(sum(2 * p["m"] * p["k"] * p["n"] for p in probs))
+    b = 0
+    while ops >= 2.0 and b < 200:
+        ops *= 0.5
+        b += 1
+    kcls = [0 if p["k"] < 1024 else (1 if p["k"] < 4096 else 2) for p in probs]
+    assert len(set(kcls)) == 3
+    table = tmp_path / "mix.txt"
+    table.write_text(f"batched {len(probs)} {b} 2 4 2\n"
+                     f"batched_class {len(probs)} {b} 0 1 1\n"
+                     f"batched_class {len(probs)} {b} 1 2 4\n"
+                     f"batched_class {len(probs)} {b} 2 3 1\n")
+    bmm.bmm_autotune_load(str(table))
+    try:
+        plan = bmm.BatchedPlan(probs)
+        announce("batched per-class mix")
+        plan.launch()
+        check(probs, host)
+        plan.destroy()
+        for pr in probs:
+            pr["C"].fill_(-1)
+        bmm.bmm_batched(probs)  # the cached, graph-replayed form of the same plan
+        check(probs, host)
+    finally:
+        bmm.bmm_finalize()  # drop the loaded records
