@@ -85,6 +85,12 @@ typedef enum {
                                        bmm_ooc); the call is then synchronous */
 #define BMM_FLAG_OOC_BLOCK_ORDER 0x10u /* out-of-core GF(2): stream the cubic block
                                           order instead of the host-level recursion */
+#define BMM_FLAG_LEAN_WORKSPACE 0x40u /* Strassen only: the depth-first levels hold one
+                                         child at a time (formed from its parent's
+                                         quadrants, its product added into the parent's
+                                         result quadrants by gamma) instead of all seven:
+                                         their workspace shrinks 7-fold, for more reads
+                                         of the parents */
 #define BMM_FLAG_INPLACE_BASIS 0x20u /* Strassen only: change A (and B when passed
                                         transposed) to the alternative basis in place
                                         and restore them afterwards, instead of
@@ -173,7 +179,8 @@ int bmm_gf2_strassen(const uint64_t* A, int64_t lda, const uint64_t* B, int64_t 
 
 /* Workspace bytes that bmm_gf2_strassen needs for these sizes and options
  * (opt->flags matter: BMM_FLAG_ALT_BASIS_IO, BMM_FLAG_INPLACE_BASIS and
- * BMM_FLAG_B_TRANSPOSED decide which operands are staged), and the depth split
+ * BMM_FLAG_B_TRANSPOSED decide which operands are staged, BMM_FLAG_LEAN_WORKSPACE how
+ * much the depth-first levels hold), and the depth split
  * it will use (either out pointer may be NULL). */
 int bmm_gf2_strassen_workspace(int64_t m, int64_t k, int64_t n, int depth,
                                const bmm_options* opt, size_t* bytes_out,

@@ -37,6 +37,7 @@ FLAG_ALT_BASIS_IO = 0x4
 FLAG_HOST_OPERANDS = 0x8
 FLAG_OOC_BLOCK_ORDER = 0x10
 FLAG_INPLACE_BASIS = 0x20
+FLAG_LEAN_WORKSPACE = 0x40
 SCHEME_SELF_INVERSE, SCHEME_CHAINING, SCHEME_WINOGRAD = 0, 1, 2
 
 _STATUS = {0: "ok", -1: "invalid argument", -2: "unsupported", -3: "workspace too small",

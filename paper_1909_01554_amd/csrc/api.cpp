@@ -309,6 +309,7 @@ struct StrassenPlan {
   int depth = 0, ds = 0, dp = 0;
   int shift = 0;  // 0: plain leaf; 1, 2: last parallel level inside the int8 leaf
                   // (2: with 8-byte operand loads)
+  bool lean = false;  // depth-first levels hold one child at a time
   int scheme = BMM_SCHEME_SELF_INVERSE;
   int64_t m = 0, kw = 0, n = 0, nw = 0;
   size_t ahat = 0, bhat = 0;
@@ -420,15 +421,18 @@ int make_plan(int64_t m, int64_t k, int64_t n, int depth, const bmm_options& o, 
     P.bhat = off;
     off = align_up(off + (size_t)n * P.kw * 8);
   }
+  // depth-first levels: all seven children of T, S and Q, or (lean) one of each
+  P.lean = (o.flags & BMM_FLAG_LEAN_WORKSPACE) != 0;
+  const size_t per = P.lean ? 1 : 7;
   for (int l = 1; l <= ds; ++l) {
     const int64_t M = m >> l, KW = P.kw >> l, N = n >> l, NW = P.nw >> l;
     Level L;
     L.T = off;
-    off = align_up(off + (size_t)7 * M * KW * 8);
+    off = align_up(off + per * M * KW * 8);
     L.S = off;
-    off = align_up(off + (size_t)7 * N * KW * 8);
+    off = align_up(off + per * N * KW * 8);
     L.Q = off;
-    off = align_up(off + (size_t)7 * M * NW * 8);
+    off = align_up(off + per * M * NW * 8);
     P.serial.push_back(L);
   }
   int left = dp - (P.shift ? 1 : 0), lvl = ds;  // levels expanded in HBM
@@ -547,6 +551,17 @@ struct StrassenRun {
     if (level >= p.ds) return parallel(level, T, ldT, S, ldS, Q, ldQ, acc);
     const int64_t M = p.m >> level, KW = p.kw >> level, N = p.n >> level, NW = p.nw >> level;
     const Level& L = p.serial[level];
+    if (p.lean) {
+      // one child at a time: T_h and S_h from the parent quadrants alpha (beta) selects,
+      // the product, then gamma adds it into the parent's result quadrants
+      for (int h = 0; h < 7; ++h) {
+        HIP_TRY(launch_child(p.scheme, 0, h, T, ldT, at(L.T), KW / 2, M, KW, s), "child T");
+        HIP_TRY(launch_child(p.scheme, 1, h, S, ldS, at(L.S), KW / 2, N, KW, s), "child S");
+        BMM_TRY(solve(level + 1, at(L.T), KW / 2, at(L.S), KW / 2, at(L.Q), NW / 2, 0));
+        HIP_TRY(launch_gamma(p.scheme, h, at(L.Q), NW / 2, Q, ldQ, M, NW, acc, s), "gamma");
+      }
+      return BMM_OK;
+    }
     HIP_TRY(launch_expand(0, T, ldT, 0, at(L.T), M, KW, 1, s, p.scheme), "serial expand T");
     HIP_TRY(launch_expand(1, S, ldS, 0, at(L.S), N, KW, 1, s, p.scheme), "serial expand S");
     const int64_t cT = (M / 2) * (KW / 2), cS = (N / 2) * (KW / 2), cQ = (M / 2) * (NW / 2);

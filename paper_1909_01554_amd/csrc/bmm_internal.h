@@ -154,6 +154,17 @@ hipError_t launch_compress2(const uint64_t* src, uint64_t* dst, int64_t ldp,
                             int64_t strideP, int64_t rows, int64_t words, int64_t parents,
                             hipStream_t s, int accumulate = 0, int scheme = 0);
 
+// One child at a time (the lean depth-first levels): child h of a parent (rows x words,
+// pitch ldp) of side 0 (left) or 1 (right, stored transposed) into dst (pitch ldd); and
+// product h (pitch lds) into the parent's result quadrants by gamma (accumulate = 1: every
+// contribution is XORed in; else each quadrant's first product overwrites it).
+uint32_t child_mask(int scheme, int side, int h);
+hipError_t launch_child(int scheme, int side, int h, const uint64_t* src, int64_t ldp,
+                        uint64_t* dst, int64_t ldd, int64_t rows, int64_t words, hipStream_t s);
+hipError_t launch_gamma(int scheme, int h, const uint64_t* src, int64_t lds, uint64_t* dst,
+                        int64_t ldp, int64_t rows, int64_t words, int accumulate,
+                        hipStream_t s);
+
 // Copy a batch of rows x words matrices (used to stage operands).
 hipError_t launch_copy(const uint64_t* src, int64_t lds, uint64_t* dst, int64_t ldd,
                        int64_t rows, int64_t words, hipStream_t s);

@@ -178,6 +178,48 @@ __global__ __launch_bounds__(256) void compress2_kernel(const uint64_t* __restri
   }
 }
 
+// One child of one parent (rows x words, pitch ldp): dst (rows/2 x words/2, pitch ldd)
+// = XOR of the parent quadrants in `mask` (bit q: quadrant q in the order 00, 01, 10, 11).
+__global__ __launch_bounds__(256) void child_kernel(const uint64_t* __restrict__ src,
+                                                    int64_t ldp, uint64_t* __restrict__ dst,
+                                                    int64_t ldd, int64_t rows, int64_t words,
+                                                    uint32_t mask) {
+  const int64_t hr = rows >> 1, hw = words >> 1;
+  const int64_t total = hr * hw;
+  const int64_t gstride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gstride) {
+    const int64_t r = e / hw;
+    const int64_t w = e - r * hw;
+    uint64_t v = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if ((mask >> q) & 1u) v ^= src[(r + (q >> 1) * hr) * ldp + (q & 1) * hw + w];
+    dst[r * ldd + w] = v;
+  }
+}
+
+// One product (rows/2 x words/2, pitch lds) into the parent's result quadrants in
+// `targets`: overwriting those in `overwrite`, XORed into the others.
+__global__ __launch_bounds__(256) void gamma_kernel(const uint64_t* __restrict__ src,
+                                                    int64_t lds, uint64_t* __restrict__ dst,
+                                                    int64_t ldp, int64_t rows, int64_t words,
+                                                    uint32_t targets, uint32_t overwrite) {
+  const int64_t hr = rows >> 1, hw = words >> 1;
+  const int64_t total = hr * hw;
+  const int64_t gstride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gstride) {
+    const int64_t r = e / hw;
+    const int64_t w = e - r * hw;
+    const uint64_t v = src[r * lds + w];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (!((targets >> q) & 1u)) continue;
+      uint64_t& d = dst[(r + (q >> 1) * hr) * ldp + (q & 1) * hw + w];
+      d = ((overwrite >> q) & 1u) ? v : (d ^ v);
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void copy_kernel(const uint64_t* __restrict__ src, int64_t lds,
                                                    uint64_t* __restrict__ dst, int64_t ldd,
                                                    int64_t rows, int64_t words) {
@@ -321,7 +363,65 @@ hipError_t compress_any(int scheme, int levels, const uint64_t* src, uint64_t* d
   }
 }
 
+// Coefficient masks of a scheme, from its own programs run on bit masks: the stored
+// quadrants child h of side `side` sums, and the products result quadrant q sums.
+template <int SCH>
+uint32_t child_mask_of(int side, int h) {
+  uint64_t o[7];
+  if (side == 0)
+    scheme::expand_one<SCH, 0>(1, 2, 4, 8, o);
+  else
+    scheme::expand_one<SCH, 1>(1, 2, 4, 8, o);
+  return (uint32_t)o[h];
+}
+template <int SCH>
+void gamma_masks_of(uint32_t (&g)[4]) {
+  const uint64_t in[7] = {1, 2, 4, 8, 16, 32, 64};
+  uint64_t c[4];
+  scheme::compress_one<SCH>(in, c[0], c[1], c[2], c[3]);
+  for (int q = 0; q < 4; ++q) g[q] = (uint32_t)c[q];
+}
+
 }  // namespace
+
+uint32_t child_mask(int scheme, int side, int h) {
+  if (scheme == BMM_SCHEME_CHAINING) return child_mask_of<BMM_SCHEME_CHAINING>(side, h);
+  if (scheme == BMM_SCHEME_WINOGRAD) return child_mask_of<BMM_SCHEME_WINOGRAD>(side, h);
+  return child_mask_of<BMM_SCHEME_SELF_INVERSE>(side, h);
+}
+
+hipError_t launch_child(int scheme, int side, int h, const uint64_t* src, int64_t ldp,
+                        uint64_t* dst, int64_t ldd, int64_t rows, int64_t words, hipStream_t s) {
+  const int64_t total = (rows >> 1) * (words >> 1);
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(child_kernel, dim3(grid_for(total)), dim3(256), 0, s, src, ldp, dst, ldd,
+                     rows, words, child_mask(scheme, side, h));
+  return hipGetLastError();
+}
+
+hipError_t launch_gamma(int scheme, int h, const uint64_t* src, int64_t lds, uint64_t* dst,
+                        int64_t ldp, int64_t rows, int64_t words, int accumulate,
+                        hipStream_t s) {
+  const int64_t total = (rows >> 1) * (words >> 1);
+  if (total <= 0) return hipSuccess;
+  uint32_t g[4];
+  if (scheme == BMM_SCHEME_CHAINING)
+    gamma_masks_of<BMM_SCHEME_CHAINING>(g);
+  else if (scheme == BMM_SCHEME_WINOGRAD)
+    gamma_masks_of<BMM_SCHEME_WINOGRAD>(g);
+  else
+    gamma_masks_of<BMM_SCHEME_SELF_INVERSE>(g);
+  uint32_t targets = 0, overwrite = 0;
+  for (int q = 0; q < 4; ++q) {
+    if (!((g[q] >> h) & 1u)) continue;
+    targets |= 1u << q;
+    // the first product of a quadrant overwrites it, unless the result accumulates
+    if (!accumulate && (g[q] & ((1u << h) - 1u)) == 0) overwrite |= 1u << q;
+  }
+  hipLaunchKernelGGL(gamma_kernel, dim3(grid_for(total)), dim3(256), 0, s, src, lds, dst, ldp,
+                     rows, words, targets, overwrite);
+  return hipGetLastError();
+}
 
 hipError_t launch_expand(int side, const uint64_t* src, int64_t ldp, int64_t strideP,
                          uint64_t* dst, int64_t rows, int64_t words, int64_t parents,

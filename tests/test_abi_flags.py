@@ -61,3 +61,16 @@ def test_shifted_leaf_plan(bmm):
                 == bmm.bmm_gf2_strassen_workspace(n, n, n, 7, ref)[0])
     with pytest.raises(bmm.BmmError):
         bmm.bmm_gf2_strassen_workspace(n, n, n, 7, bmm.Options(shift=3))
+
+
+def test_lean_workspace_plan(bmm):
+    """The lean depth-first levels hold one child of T, S and Q instead of seven: at
+    n = 2^18, depth 7 (3 + 4) the serial levels drop from 7 * 3 * (2 + 0.5 + 0.125) GiB to
+    a seventh of that."""
+    n = 1 << 18
+    base = dict(depth_serial=3, depth_parallel=4, leaf=2)
+    full = bmm.bmm_gf2_strassen_workspace(n, n, n, 7, bmm.Options(**base))[0]
+    lean = bmm.bmm_gf2_strassen_workspace(
+        n, n, n, 7, bmm.Options(flags=bmm.FLAG_LEAN_WORKSPACE, **base))[0]
+    serial = sum(3 * ((n >> l) ** 2 // 8) for l in (1, 2, 3))
+    assert full - lean == 6 * serial

@@ -459,3 +459,37 @@ def test_strassen_errors(bmm):
         bmm.bmm_gf2_strassen(A, A[:, :], C, 1024, 1024, 1024, big, depth=2, b_transposed=True,
                              inplace_basis=True)
     assert e.value.status == -1
+
+
+LEAN_CASES = [  # m, k, n, depth, depth_serial
+    (1024, 1024, 1024, 2, 1), (2048, 2048, 2048, 3, 2), (2048, 4096, 1024, 4, 3),
+    (4096, 4096, 4096, 5, 2), (768, 1536, 1024, 1, 1),
+]
+
+
+@pytest.mark.parametrize("m,k,n,depth,ds", LEAN_CASES)
+@pytest.mark.parametrize("scheme", [0, 1, 2])
+@pytest.mark.parametrize("accumulate", [False, True])
+def test_strassen_lean_serial_levels(bmm, m, k, n, depth, ds, scheme, accumulate):
+    """BMM_FLAG_LEAN_WORKSPACE: the depth-first levels form one child at a time from the
+    parent's quadrants and add each product into the parent's result quadrants; the
+    product is the same and the workspace's serial part is a seventh."""
+    import torch
+    seed = 700 + m + depth + 3 * scheme + (1 if accumulate else 0)
+    A = bmmgen.fill_cpu(m, k, seed, bmmgen.TAG_A, bmmgen.Dist.half())
+    B = bmmgen.fill_cpu(k, n, seed, bmmgen.TAG_B, bmmgen.Dist.half())
+    C0 = bmmgen.fill_cpu(m, n, seed, 0xC, bmmgen.Dist.half())
+    opts = bmm.Options(leaf=2, depth_serial=ds, depth_parallel=depth - ds, scheme=scheme,
+                       flags=bmm.FLAG_LEAN_WORKSPACE)
+    full = bmm.bmm_gf2_strassen_workspace(
+        m, k, n, depth, bmm.Options(leaf=2, depth_serial=ds, depth_parallel=depth - ds,
+                                    scheme=scheme))[0]
+    nbytes, _, _ = bmm.bmm_gf2_strassen_workspace(m, k, n, depth, opts)
+    assert nbytes < full
+    ws = torch.empty(nbytes // 8 + 1, dtype=torch.int64, device="cuda")
+    Cd = to_dev(C0) if accumulate else empty_dev(m, words(n), fill=-1)
+    announce("strassen lean", m, k, n, depth, ds, scheme, accumulate)
+    bmm.bmm_gf2_strassen(to_dev(A), to_dev(B), Cd, m, k, n, ws, depth=depth, options=opts,
+                         accumulate=accumulate)
+    prod = oracle.mul(A, B, k, n, oracle.GF2)
+    assert np.array_equal(from_dev(Cd), (C0 ^ prod) if accumulate else prod)
