@@ -119,7 +119,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows-1core", type=int, default=16,
                     help="rows of the GF(2) product the oracle computes on one thread")
-    ap.add_argument("--freivalds", type=int, default=2,
+    ap.add_argument("--freivalds", type=int, default=20,
                     help="Freivalds vectors checking the whole GF(2) product on the host")
     ap.add_argument("--leaf", choices=["mfma", "valu", "f4"], default="mfma",
                     help="leaf of the timed steps (mfma = int8 MFMA, f4 = E2M1 MFMA)")
