@@ -135,6 +135,13 @@ def parse():
                          "persistent launch; ooc: host-resident operands; valu: the VALU "
                          "issue-rate calibration and the VALU leaf on both semirings; small: "
                          "n = 2048 full products, graph-replayed, against the oracle")
+    ap.add_argument("--k-panel", type=int, default=0,
+                    help="leaf mode: k-panel length of the Boolean leaf in bits (0: one panel)")
+    ap.add_argument("--dense", action="store_true",
+                    help="leaf mode: dense Bernoulli(1/2) operands instead of the sparse ones")
+    ap.add_argument("--dense-k-panel", type=int, default=16384,
+                    help="step: also time the dense Boolean leaf with this k-panel length "
+                         "(bits; 0 skips it)")
     ap.add_argument("--problems", type=int, default=4096, help="batched mode: problem count")
     ap.add_argument("--block", type=int, default=1 << 17, help="ooc mode: block size (bits)")
     return ap.parse_args()
@@ -607,19 +614,24 @@ def main():
                            args.depth - args.depth_serial, shift=args.shift)
 
     if args.mode == "leaf":
-        bmm.bmm_transpose(Bb, BTb, n, n)
+        # one Boolean leaf launch (or one per k panel) on the sparse headline operands, or
+        # on the dense GF(2) ones, then a 4 GiB copy that calibrates the traffic counters
+        LA, LB = (Ag, Bg) if args.dense else (Ab, Bb)
+        bmm.bmm_transpose(LB, BTb, n, n)
         src = torch.empty(1 << 29, dtype=torch.int64, device=dev)  # 4 GiB
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
         e = events()
         e[0].record(stream)
-        bmm.bmm_boolean(Ab, BTb, Cb, n, n, n, options=bmm.Options(leaf=LEAF[args.leaf],
-                        tile=args.tile), b_transposed=True)
+        bmm.bmm_boolean(LA, BTb, Cb, n, n, n, options=bmm.Options(
+            leaf=LEAF[args.leaf], tile=args.tile, k_panel=args.k_panel or -1), b_transposed=True)
         e[1].record(stream)
         dst.copy_(src)
         e[2].record(stream)
         torch.cuda.synchronize()
         print(json.dumps({"mode": "leaf", "n": n, "leaf": args.leaf,
+                          "operands": "dense" if args.dense else "sparse",
+                          "k_panel": args.k_panel or n,
                           "leaf_s": e[0].elapsed_time(e[1]) / 1e3,
                           "copy_bytes": 2 * src.numel() * 8,
                           "copy_s": e[1].elapsed_time(e[2]) / 1e3}), flush=True)
@@ -813,6 +825,21 @@ def main():
     dense = {"bits": "Bernoulli(1/2)", "leaf_s": round(dense_s, 4),
              "pbops": round(bops / dense_s / 1e15, 4), "sclk_ghz": ck.mean_ghz()}
     log(f"[bench] Boolean leaf on dense operands {dense_s:.3f} s")
+    if args.dense_k_panel > 0:
+        # the same product in k panels: each panel's operand rows stay in L2 while the
+        # tiles that share them run, which cuts memory traffic and the power it draws
+        kopt = opts(LEAF[args.leaf])
+        kopt.k_panel = args.dense_k_panel
+        e = events()
+        with ClockSampler() as ck:
+            e[0].record(stream)
+            bmm.bmm_boolean(Ag, BTb, Cb, n, n, n, options=kopt, b_transposed=True)
+            e[1].record(stream)
+            torch.cuda.synchronize()
+        kp_s = e[0].elapsed_time(e[1]) / 1e3
+        dense["k_panel"] = {"bits": args.dense_k_panel, "leaf_s": round(kp_s, 4),
+                            "pbops": round(bops / kp_s / 1e15, 4), "sclk_ghz": ck.mean_ghz()}
+        log(f"[bench] ... in k panels of {args.dense_k_panel} bits {kp_s:.3f} s")
 
     # Rows of both products, checked against the oracle; the GF(2) rows time the oracle.
     cpu = None

@@ -112,6 +112,15 @@ typedef struct {
                          (else off).  Applies where the leaf is int8, the scheme is not
                          Winograd, depth_parallel >= 1 and a leaf's k is 2048 or 4096
                          bits; elsewhere the plain leaf runs */
+  int64_t k_panel;    /* cubic products (bmm_gf2, bmm_boolean, bmm_cubic_noalloc): k is
+                         taken in panels of this many bits (rounded up to whole words),
+                         one leaf launch per panel, each panel's product XORed / ORed
+                         into C after the first (the sum over j split into consecutive
+                         ranges).  Shorter panels keep the operand rows that neighbouring
+                         tiles share inside L2 and cut memory traffic, at the price of
+                         rereading C once per panel.  0 = the k-panel table's record for
+                         the shape (bmm_autotune_k_panel), else one panel; negative = one
+                         panel.  Multiples of 128 bits keep 16-byte operand loads */
 } bmm_options;
 
 /* Fill *opt with the defaults (everything automatic, no flags). */
@@ -333,7 +342,8 @@ int bmm_leaf_choice(int semiring, int64_t m, int64_t k, int64_t n, int64_t batch
  * and, where it applies, with the last level shifted into the leaf (shift 1 and 2),
  * each with the fewest depth-first levels whose workspace fits, and records the
  * fastest (depth, split, shift) for depth -1.
- * Both tables are per process and can be saved to / loaded from a text file. */
+ * The tables (these two, the k-panel table below and the batched plans' records) are
+ * per process and can be saved to / loaded from a text file. */
 int bmm_autotune_leaf(int semiring, int64_t m, int64_t k, int64_t n, int64_t batch,
                       int* leaf_out, int* tile_out, double* seconds_out);
 int bmm_autotune_cubic(int semiring, int64_t m, int64_t k, int64_t n, int* leaf_out,
@@ -345,6 +355,17 @@ int bmm_autotune_strassen(const uint64_t* A, int64_t lda, const uint64_t* B, int
                           void* workspace, size_t workspace_bytes, const bmm_options* opt,
                           int* depth_out, int* depth_serial_out, int* shift_out,
                           double* seconds_out);
+/* k-panel table: times bmm_gf2 / bmm_boolean on the caller's device operands (B as
+ * opt->flags say; BMM_FLAG_ACCUMULATE and BMM_FLAG_HOST_OPERANDS are BMM_E_INVAL)
+ * with each candidate panel length (candidates[0..count-1] in bits; count 0: one
+ * panel and every power of two from 8192 below k), once after one warm-up, and
+ * records the fastest for k_panel = 0.  The result depends on the operands' bits
+ * (dense operands draw more power, which the shorter panels' lower memory traffic
+ * relieves), so tune on representative data.  C holds the product on return. */
+int bmm_autotune_k_panel(int semiring, const uint64_t* A, int64_t lda, const uint64_t* B,
+                         int64_t ldb, uint64_t* C, int64_t ldc, int64_t m, int64_t k, int64_t n,
+                         const bmm_options* opt, const int64_t* candidates, int count,
+                         int64_t* panel_out, double* seconds_out);
 int bmm_autotune_save(const char* path);
 int bmm_autotune_load(const char* path);
 

@@ -70,14 +70,16 @@ _int = ctypes.c_int
 
 
 class Options(ctypes.Structure):
-    """bmm_options: leaf, tile, depth_serial, depth_parallel, block, flags, scheme, shift."""
+    """bmm_options: leaf, tile, depth_serial, depth_parallel, block, flags, scheme, shift,
+    k_panel."""
     _fields_ = [("leaf", _int), ("tile", _int), ("depth_serial", _int),
                 ("depth_parallel", _int), ("block", _i64), ("flags", ctypes.c_uint32),
-                ("scheme", _int), ("shift", _int)]
+                ("scheme", _int), ("shift", _int), ("k_panel", _i64)]
 
     def __init__(self, leaf=LEAF_AUTO, tile=0, depth_serial=-1, depth_parallel=-1, block=0,
-                 flags=0, scheme=0, shift=-1):
-        super().__init__(leaf, tile, depth_serial, depth_parallel, block, flags, scheme, shift)
+                 flags=0, scheme=0, shift=-1, k_panel=0):
+        super().__init__(leaf, tile, depth_serial, depth_parallel, block, flags, scheme, shift,
+                         k_panel)
 
 
 class Problem(ctypes.Structure):
@@ -130,6 +132,10 @@ _c_tune_strassen = _sig("bmm_autotune_strassen",
                          ctypes.c_size_t, ctypes.POINTER(Options), ctypes.POINTER(_int),
                          ctypes.POINTER(_int), ctypes.POINTER(_int),
                          ctypes.POINTER(ctypes.c_double)])
+_c_tune_kpanel = _sig("bmm_autotune_k_panel",
+                      [_int, _vp, _i64, _vp, _i64, _vp, _i64, _i64, _i64, _i64,
+                       ctypes.POINTER(Options), ctypes.POINTER(_i64), _int, ctypes.POINTER(_i64),
+                       ctypes.POINTER(ctypes.c_double)])
 _c_tune_save = _sig("bmm_autotune_save", [ctypes.c_char_p])
 _c_tune_load = _sig("bmm_autotune_load", [ctypes.c_char_p])
 _c_tiles = _sig("bmm_leaf_tiles", [_int, ctypes.POINTER(_int)])
@@ -514,6 +520,23 @@ def bmm_autotune_strassen(A, B, C, m, k, n, workspace, options=None):
                             _ptr(workspace), nbytes, ctypes.byref(o), ctypes.byref(d),
                             ctypes.byref(ds), ctypes.byref(sh), ctypes.byref(secs)))
     return d.value, ds.value, sh.value, secs.value
+
+
+def bmm_autotune_k_panel(semiring, A, B, C, m, k, n, options=None, candidates=None,
+                         b_transposed=False):
+    """Time the cubic product on these operands with each k-panel length (bits;
+    default: one panel and the powers of two from 8192 below k); returns
+    (panel_bits, seconds) and records the choice for k_panel = 0.  C holds the product."""
+    o = _opts(options, FLAG_B_TRANSPOSED if b_transposed else 0)
+    _operands(A, B, C, m, k, n, bool(o.flags & FLAG_B_TRANSPOSED))
+    cand = list(candidates or [])
+    arr = (_i64 * max(1, len(cand)))(*cand)
+    bits = _i64(0)
+    secs = ctypes.c_double(0.0)
+    _check(_c_tune_kpanel(semiring, _ptr(A), _ld(A), _ptr(B), _ld(B), _ptr(C), _ld(C), m, k, n,
+                          ctypes.byref(o), arr, len(cand), ctypes.byref(bits),
+                          ctypes.byref(secs)))
+    return bits.value, secs.value
 
 
 def bmm_autotune_set(semiring, m, k, n, leaf, tile, batch=1):

@@ -137,6 +137,9 @@ struct TuneVal {
 std::map<TuneKey, TuneVal> g_tune;
 // Strassen (depth, serial depth, shifted leaf level) per shape, from bmm_autotune_strassen.
 std::map<std::tuple<int64_t, int64_t, int64_t>, std::tuple<int, int, int>> g_depth;
+// Cubic k-panel schedule per (semiring, m, k, n): panel length in bits, from
+// bmm_autotune_k_panel.
+std::map<std::tuple<int, int64_t, int64_t, int64_t>, int64_t> g_kpanel;
 // Batched plans: (problem count, floor(log2(total ops))) -> (leaf, tile, workgroups per CU).
 std::map<std::pair<int64_t, int>, std::tuple<int, int, int>> g_batched;
 // Per size class of k within such plans: (count, floor(log2(total ops)), class) ->
@@ -231,6 +234,20 @@ int validate_product(const uint64_t* A, int64_t lda, const uint64_t* B, int64_t 
 
 namespace bmm {
 
+// Panel length (bits) of a cubic product's k: the options' own (rounded up to whole
+// words; negative = one panel), else the k-panel table's record, else one panel.
+int64_t k_panel_bits(int semiring, int64_t m, int64_t k, int64_t n, const bmm_options& o) {
+  int64_t bits = 0;
+  if (o.k_panel > 0) {
+    bits = (o.k_panel + 63) / 64 * 64;
+  } else if (o.k_panel == 0) {
+    std::lock_guard<std::mutex> lock(g_mu);
+    auto it = g_kpanel.find({semiring, m, k, n});
+    if (it != g_kpanel.end()) bits = it->second;
+  }
+  return bits > 0 && bits < k ? bits : std::max<int64_t>(k, 1);
+}
+
 int cubic_product(int semiring, const uint64_t* A, int64_t lda, const uint64_t* B, int64_t ldb,
                   uint64_t* C, int64_t ldc, int64_t m, int64_t k, int64_t n,
                   const bmm_options* opt, void* stream, const BtScratch* caller_bt) {
@@ -265,8 +282,16 @@ int cubic_product(int semiring, const uint64_t* A, int64_t lda, const uint64_t* 
   }
   int leaf, tile;
   pick_leaf(semiring, m, k, n, 1, o, &leaf, &tile);
-  LeafBatch p{A, lda, 0, BT, ldbt, 0, C, ldc, 0, m, k, n, 1, acc ? 1 : 0};
-  return run_leaf(semiring, leaf, tile, p, s);
+  // k in panels: C = sum over panels of A[:, panel] B[panel, :], each panel's product
+  // added into C (XOR or OR) after the first; the leaf and tile are the full shape's
+  const int64_t panel = k_panel_bits(semiring, m, k, n, o);
+  for (int64_t p0 = 0; p0 < k; p0 += panel) {
+    const int64_t kp = std::min(panel, k - p0);
+    LeafBatch p{A + p0 / 64, lda, 0, BT + p0 / 64, ldbt, 0, C, ldc, 0, m, kp, n, 1,
+                (acc || p0 > 0) ? 1 : 0};
+    BMM_TRY(run_leaf(semiring, leaf, tile, p, s));
+  }
+  return BMM_OK;
 }
 
 }  // namespace bmm
@@ -587,6 +612,7 @@ void bmm_options_init(bmm_options* opt) {
   opt->flags = 0;
   opt->scheme = BMM_SCHEME_SELF_INVERSE;
   opt->shift = -1;
+  opt->k_panel = 0;
 }
 
 int bmm_gf2(const uint64_t* A, int64_t lda, const uint64_t* B, int64_t ldb, uint64_t* C,
@@ -1067,6 +1093,74 @@ int bmm_autotune_strassen(const uint64_t* A, int64_t lda, const uint64_t* B, int
   return BMM_OK;
 }
 
+int bmm_autotune_k_panel(int semiring, const uint64_t* A, int64_t lda, const uint64_t* B,
+                         int64_t ldb, uint64_t* C, int64_t ldc, int64_t m, int64_t k, int64_t n,
+                         const bmm_options* opt, const int64_t* candidates, int count,
+                         int64_t* panel_out, double* seconds_out) {
+  if (semiring != BMM_GF2 && semiring != BMM_BOOLEAN)
+    return fail(BMM_E_INVAL, "unknown semiring %d", semiring);
+  bmm_options o = opt ? *opt : defaults();
+  if (o.flags & (BMM_FLAG_ACCUMULATE | BMM_FLAG_HOST_OPERANDS))
+    return fail(BMM_E_INVAL, "k-panel tuning runs the product repeatedly on device "
+                "operands: accumulation and host operands are not allowed");
+  if (count < 0 || (count > 0 && !candidates)) return fail(BMM_E_INVAL, "bad candidate list");
+  if (m <= 0 || n <= 0 || k <= 0) return fail(BMM_E_INVAL, "k-panel tuning needs a nonempty product");
+  // candidates: the caller's, else one panel and every power of two from 8192 bits below k
+  std::vector<int64_t> cand;
+  if (count > 0) {
+    for (int i = 0; i < count; ++i) {
+      if (candidates[i] <= 0) return fail(BMM_E_INVAL, "candidate %d is not positive", i);
+      cand.push_back(std::min<int64_t>((candidates[i] + 63) / 64 * 64, k));
+    }
+  } else {
+    cand.push_back(k);
+    for (int64_t b = (int64_t)1 << 40; b >= 8192; b >>= 1)
+      if (b < k) cand.push_back(b);
+  }
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(BMM_E_DEVICE, "hipEventCreate failed");
+  }
+  double best = 1e30;
+  int64_t best_bits = k;
+  int rc = BMM_OK;
+  auto product = [&](const bmm_options* t) {
+    return cubic(semiring, A, lda, B, ldb, C, ldc, m, k, n, t, nullptr);
+  };
+  for (size_t i = 0; i < cand.size() && rc == BMM_OK; ++i) {
+    bmm_options t = o;
+    t.k_panel = cand[i];
+    if (i == 0) rc = product(&t);  // warm-up (B^T scratch, code objects)
+    if (rc != BMM_OK) break;
+    (void)hipEventRecord(e0, nullptr);
+    rc = product(&t);
+    (void)hipEventRecord(e1, nullptr);
+    if (rc != BMM_OK) break;
+    if (hipEventSynchronize(e1) != hipSuccess) {
+      rc = check_hip(hipGetLastError(), "autotune sync");
+      break;
+    }
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (ms * 1e-3 < best) {
+      best = ms * 1e-3;
+      best_bits = cand[i];
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != BMM_OK) return rc;
+  {
+    std::lock_guard<std::mutex> lock(g_mu);
+    g_kpanel[{semiring, m, k, n}] = best_bits;
+  }
+  if (panel_out) *panel_out = best_bits;
+  if (seconds_out) *seconds_out = best;
+  return BMM_OK;
+}
+
 int bmm_autotune_save(const char* path) {
   if (!path) return fail(BMM_E_INVAL, "null path");
   std::ofstream f(path);
@@ -1076,7 +1170,8 @@ int bmm_autotune_save(const char* path) {
        "# leaf semiring m k n batch_bucket best_leaf tile_valu tile_mfma_i8 tile_mfma_f4\n"
        "# depth m k n depth depth_serial shift\n"
        "# batched count log2_ops leaf tile workgroups_per_cu\n"
-       "# batched_class count log2_ops k_class leaf tile\n";
+       "# batched_class count log2_ops k_class leaf tile\n"
+       "# kpanel semiring m k n panel_bits\n";
   for (auto& [key, val] : g_tune)
     f << "leaf " << key.semiring << ' ' << key.m << ' ' << key.k << ' ' << key.n << ' '
       << key.batch << ' ' << val.best_leaf << ' ' << val.tile[1] << ' ' << val.tile[2] << ' '
@@ -1090,6 +1185,9 @@ int bmm_autotune_save(const char* path) {
   for (auto& [key, val] : g_bclass)
     f << "batched_class " << std::get<0>(key) << ' ' << std::get<1>(key) << ' '
       << std::get<2>(key) << ' ' << val.first << ' ' << val.second << '\n';
+  for (auto& [key, val] : g_kpanel)
+    f << "kpanel " << std::get<0>(key) << ' ' << std::get<1>(key) << ' ' << std::get<2>(key)
+      << ' ' << std::get<3>(key) << ' ' << val << '\n';
   return f ? BMM_OK : fail(BMM_E_INVAL, "write failed: %s", path);
 }
 
@@ -1122,6 +1220,12 @@ int bmm_autotune_load(const char* path) {
         return fail(BMM_E_INVAL, "bad depth line: %s", line.c_str());
       std::lock_guard<std::mutex> lock(g_mu);
       g_depth[{m, k, n}] = {d, ds, sh};
+    } else if (sscanf(line.c_str(), "kpanel %d %lld %lld %lld %lld", &sr, &m, &k, &n, &b) == 5) {
+      if ((sr != BMM_GF2 && sr != BMM_BOOLEAN) || m <= 0 || k <= 0 || n <= 0 || b <= 0 ||
+          b % 64 != 0)
+        return fail(BMM_E_INVAL, "bad kpanel line: %s", line.c_str());
+      std::lock_guard<std::mutex> lock(g_mu);
+      g_kpanel[{sr, m, k, n}] = b;
     } else if (sscanf(line.c_str(), "batched_class %lld %d %d %d %d", &m, &d, &ds, &leaf, &t1) ==
                5) {
       if (m <= 0 || d < 0 || ds < 0 || ds > 2 || leaf < BMM_LEAF_VALU || leaf > BMM_LEAF_MFMA_F4 ||

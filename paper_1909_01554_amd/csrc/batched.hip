@@ -95,25 +95,18 @@ __device__ __forceinline__ void run_item(const BatchedDesc& d, int64_t item, int
   }
 }
 
-// LDS-staged item (tile 4): mfma::lds_item (operand rows of the workgroup's 2 x 2
-// wave tiles staged through LDS once per stage and shared by the four waves).
-template <int FMT>
-__device__ __forceinline__ void run_item_lds(const BatchedDesc& d, int64_t item, int w,
-                                             unsigned char* smem) {
-  int64_t im, in;
-  band_coord(item, d.items_m, d.items_n, im, in);
-  mfma::lds_item<mfma::SEMI_ANY, FMT, kWide>(d.A, d.lda, d.BT, d.ldbt, d.C, d.ldc, d.m, d.k,
-                                             d.n, im, in, d.tiles_m, d.tiles_n, d.aligned != 0,
-                                             0, d.semiring, w, smem);
-}
-
+// LDS-staged items (tile 4): mfma::lds_item (operand rows of the workgroup's 2 x 2
+// wave tiles staged through LDS once per stage and shared by the four waves).  (Loading
+// the next item's first stage during the current item's epilogue measured slower: wave
+// 0 then has to name the next item before the last stage's barrier, which the other
+// waves wait for.)
 template <int FMT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void batched_lds_kernel(
     const BatchedDesc* __restrict__ descs, const BatchedSeg* __restrict__ segs,
     BatchedQueues qs, unsigned int* __restrict__ counters) {
   __shared__ int slots[2][2];
   __shared__ __attribute__((aligned(16))) unsigned char smem[mfma::kLdsItemBytes];
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   int q = blockIdx.x % kXcds, visited = 0;  // wave 0's queue state
   if (w == 0) {
     unsigned v = 0;
@@ -121,6 +114,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
     resolve_item(segs, qs, counters, __shfl(v, 0), q, visited, lane, slots[0]);
   }
   __syncthreads();
+  mfma::LdsStage stage;
   for (int it = 0;; ++it) {
     const int* cur = slots[it & 1];
     const int p = __builtin_amdgcn_readfirstlane(cur[0]);
@@ -129,7 +123,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
     unsigned v = 0;
     if (w == 0 && lane == 0 && visited < kXcds)
       v = atomicAdd(&counters[q * kBatchedCounterStride], 1u);
-    run_item_lds<FMT>(descs[p], item, w, smem);
+    const BatchedDesc& d = descs[p];
+    int64_t im, in;
+    band_coord(item, d.items_m, d.items_n, im, in);
+    mfma::lds_item<mfma::SEMI_ANY, FMT, kWide>(d.A, d.lda, d.BT, d.ldbt, d.C, d.ldc, d.m, d.k,
+                                               d.n, im, in, d.tiles_m, d.tiles_n,
+                                               d.aligned != 0, 0, d.semiring, w, smem, stage);
     if (w == 0) resolve_item(segs, qs, counters, __shfl(v, 0), q, visited, lane, slots[(it + 1) & 1]);
     __syncthreads();
   }
@@ -141,7 +140,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
     BatchedQueues qs, unsigned int* __restrict__ counters) {
   // two (problem, item) slots: wave 0 fills one while the others read the other
   __shared__ int slots[2][2];
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   int q = blockIdx.x % kXcds, visited = 0;  // wave 0's queue state
   if (w == 0) {
     unsigned v = 0;

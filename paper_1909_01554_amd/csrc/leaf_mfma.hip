@@ -32,7 +32,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void l
     LeafBatch p, int64_t tiles_m, int64_t tiles_n) {
   const int64_t grid_m = (tiles_m + 1) >> 1, grid_n = (tiles_n + 1) >> 1;
   const TileCoord c = xcd_tile(blockIdx.x, gridDim.x, grid_m, grid_n);
-  const int w = threadIdx.x >> 6;
+  // The wide tiles take the wave index as a uniform value (their tile coordinates then
+  // live in scalar registers, which frees the vector registers the long-k loop spilled);
+  // the narrower tiles keep the per-lane form, measured faster on the recursion's leaves.
+  const int w = RB == 4 ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : threadIdx.x >> 6;
   const int64_t tm = 2 * c.tm + (w >> 1);
   const int64_t tn = 2 * c.tn + (w & 1);
   if (c.b >= p.batch || tm >= tiles_m || tn >= tiles_n) return;  // uniform per wave
@@ -52,10 +55,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void l
   const int64_t grid_m = (tiles_m + 1) >> 1, grid_n = (tiles_n + 1) >> 1;
   const TileCoord c = xcd_tile(blockIdx.x, gridDim.x, grid_m, grid_n);
   if (c.b >= p.batch) return;  // uniform per workgroup
+  mfma::LdsStage stage;
   mfma::lds_item<SEMI, FMT, WIDE>(p.A + c.b * p.strideA, p.lda, p.BT + c.b * p.strideB, p.ldbt,
                                   p.C + c.b * p.strideC, p.ldc, p.m, p.k, p.n, c.tm, c.tn,
                                   tiles_m, tiles_n, aligned != 0, p.accumulate, SEMI,
-                                  threadIdx.x >> 6, smem);
+                                  __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), smem, stage);
 }
 
 template <int SEMI, int FMT>

@@ -99,7 +99,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void l
   __shared__ uint32_t acc_bits[kWaves][4][RA * RB][32];
   const int64_t grid_m = (tiles_m + 1) >> 1, grid_n = (tiles_n + 1) >> 1;
   const TileCoord c = xcd_tile(blockIdx.x, gridDim.x, grid_m, grid_n);
-  const int w = threadIdx.x >> 6;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wave
   const int64_t tm = 2 * c.tm + (w >> 1);
   const int64_t tn = 2 * c.tn + (w & 1);
   if (c.b >= p.parents || tm >= tiles_m || tn >= tiles_n) return;  // uniform per wave

@@ -29,6 +29,9 @@ constexpr int SEMI_ANY = -1;
 #define BMM_GLOBAL __attribute__((address_space(1)))
 typedef const BMM_GLOBAL uint64_t* gq_ptr;
 typedef BMM_GLOBAL uint32_t* gd_ptr;
+typedef BMM_GLOBAL uint64_t* gw_ptr;
+typedef uint64_t cpair_t __attribute__((ext_vector_type(2)));
+typedef BMM_GLOBAL cpair_t* gw2_ptr;
 
 template <int FMT>
 struct Acc;
@@ -136,7 +139,11 @@ __device__ __forceinline__ void mfma_word(const uint64_t (&xa)[RA], const uint64
 }
 
 // Epilogue of a TM x TN wave tile (TM = 32*RA, TN = 32*RB) at tile coordinates
-// (tm, tn): reduce counts to bits and pack 32 columns per dword with ballots.
+// (tm, tn): reduce counts to bits and pack 32 columns per dword with ballots.  A tile
+// of TN = 128 owns two whole 64-bit words of every row: it stores them as one 16-byte
+// piece where C's rows are 16-byte aligned (else as two words), so each C line is
+// written in fewer, larger pieces.  Narrower tiles store each dword as it is formed
+// (measured faster on the recursion's short 128 x 64 tiles than gathering the words).
 template <int SEMI, int RA, int RB, int FMT>
 __device__ __forceinline__ void epilogue(const typename Acc<FMT>::type (&acc)[RA][RB],
                                          uint64_t* __restrict__ Cm, int64_t ldc, int64_t m,
@@ -144,23 +151,59 @@ __device__ __forceinline__ void epilogue(const typename Acc<FMT>::type (&acc)[RA
                                          int semiring = SEMI) {
   constexpr int TM = 32 * RA, TN = 32 * RB;
   const bool gf2 = SEMI == SEMI_ANY ? semiring == GF2 : SEMI == GF2;
-  const int lane = threadIdx.x & 63;
-  const int half = lane >> 5;
-  const int li = lane & 31;
-  const gd_ptr C32 = (gd_ptr)Cm;
-  const int64_t ldc32 = 2 * ldc;
   const int64_t n_words32 = ((n + 63) >> 6) * 2;  // dwords per C row incl. padding
-  const int myv = ((li >> 3) << 2) | (li & 3);
-  const int myhi = (li >> 2) & 1;
+  if constexpr (RB != 4) {
+    const int lane = threadIdx.x & 63;
+    const int half = lane >> 5;
+    const int li = lane & 31;
+    const gd_ptr C32 = (gd_ptr)Cm;
+    const int64_t ldc32 = 2 * ldc;
+    const int myv = ((li >> 3) << 2) | (li & 3);
+    const int myhi = (li >> 2) & 1;
 #pragma unroll
-  for (int g = 0; g < RB; ++g) {
-    const int64_t c0 = tn * TN + 32 * g;
-    const int64_t cw = c0 >> 5;
-    if (cw >= n_words32) continue;  // uniform
-    const int64_t valid = n - c0;
-    const uint32_t cmask = valid >= 32 ? 0xFFFFFFFFu : (valid > 0 ? ((1u << valid) - 1u) : 0u);
+    for (int g = 0; g < RB; ++g) {
+      const int64_t c0 = tn * TN + 32 * g;
+      const int64_t cw = c0 >> 5;
+      if (cw >= n_words32) continue;  // uniform
+      const int64_t valid = n - c0;
+      const uint32_t cmask = valid >= 32 ? 0xFFFFFFFFu : (valid > 0 ? ((1u << valid) - 1u) : 0u);
 #pragma unroll
-    for (int f = 0; f < RA; ++f) {
+      for (int f = 0; f < RA; ++f) {
+        uint32_t mine = 0;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          int cnt;
+          if constexpr (FMT == FMT_F4)
+            cnt = __float2int_rn(acc[f][g][v] * 4.0f);  // exact: a multiple of 0.25
+          else
+            cnt = acc[f][g][v];
+          const bool bit = gf2 ? ((cnt & 1) != 0) : (cnt != 0);
+          const uint64_t bal = __ballot(bit);
+          const uint32_t word = myhi ? (uint32_t)(bal >> 32) : (uint32_t)bal;
+          mine = (myv == v) ? word : mine;
+        }
+        mine &= cmask;
+        const int64_t row = tm * TM + 32 * f + li;
+        if (half == 0 && row < m) {
+          const gd_ptr dst = C32 + row * ldc32 + cw;
+          if (accumulate) mine = gf2 ? (mine ^ *dst) : (mine | *dst);
+          *dst = mine;
+        }
+      }
+    }
+  } else {
+    // the lane index is taken afresh here (not from the work-item id the main loop
+    // used), so nothing derived from it has to stay live across the loop
+    const int lane = (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+    const int half = lane >> 5;
+    const int li = lane & 31;
+    const int myv = ((li >> 3) << 2) | (li & 3);
+    const int hshift = ((li >> 2) & 1) * 32;  // lanes 4..7 of every 8 take the upper half
+    // the 32-column dword of block (f, g) for this lane's row (lane li of half 0 keeps
+    // row 32 f + li)
+    auto pack = [&](int f, int g) -> uint32_t {
+      const int64_t valid = n - (tn * TN + 32 * g);
+      const uint32_t cmask = valid >= 32 ? 0xFFFFFFFFu : (valid > 0 ? ((1u << valid) - 1u) : 0u);
       uint32_t mine = 0;
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
@@ -171,15 +214,46 @@ __device__ __forceinline__ void epilogue(const typename Acc<FMT>::type (&acc)[RA
           cnt = acc[f][g][v];
         const bool bit = gf2 ? ((cnt & 1) != 0) : (cnt != 0);
         const uint64_t bal = __ballot(bit);
-        const uint32_t word = myhi ? (uint32_t)(bal >> 32) : (uint32_t)bal;
+        const uint32_t word = (uint32_t)(bal >> hshift);  // one 64-bit shift per lane
         mine = (myv == v) ? word : mine;
       }
-      mine &= cmask;
+      return mine & cmask;
+    };
+    const gw_ptr C64 = (gw_ptr)Cm;
+    const int64_t n_words = n_words32 >> 1;
+    const int64_t w0 = tn * 2;  // first 64-bit word of the tile's columns
+    if (w0 >= n_words) return;  // uniform
+    const bool vec16 = w0 + 1 < n_words &&
+                       ((reinterpret_cast<uintptr_t>(Cm) & 15) | (uintptr_t)(ldc & 1)) == 0;
+#pragma unroll
+    for (int f = 0; f < RA; ++f) {
+      // one row block at a time: the scheduler would otherwise hoist every block's
+      // ballots ahead of the stores and park the masks in VGPR lanes
+      __builtin_amdgcn_sched_barrier(0);
+      uint64_t word[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+        word[h] = (uint64_t)pack(f, 2 * h) | ((uint64_t)pack(f, 2 * h + 1) << 32);
       const int64_t row = tm * TM + 32 * f + li;
       if (half == 0 && row < m) {
-        const gd_ptr dst = C32 + row * ldc32 + cw;
-        if (accumulate) mine = gf2 ? (mine ^ *dst) : (mine | *dst);
-        *dst = mine;
+        const gw_ptr dst = C64 + row * ldc + w0;
+        if (vec16) {
+          const gw2_ptr d2 = (gw2_ptr)dst;
+          cpair_t x = {word[0], word[1]};
+          if (accumulate) {
+            const cpair_t old = *d2;
+            x = gf2 ? (x ^ old) : (x | old);
+          }
+          *d2 = x;
+        } else {
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            if (w0 + h >= n_words) break;  // uniform
+            uint64_t x = word[h];
+            if (accumulate) x = gf2 ? (x ^ dst[h]) : (x | dst[h]);
+            dst[h] = x;
+          }
+        }
       }
     }
   }
@@ -277,10 +351,14 @@ __device__ __forceinline__ void tile(const uint64_t* __restrict__ A, int64_t lda
     epilogue<SEMI, RA, RB, FMT>(acc, Cm, ldc, m, n, tm, tn, accumulate, semiring);
     return;
   }
+  // words by which the row pointers have been moved forward (the chunked loop below
+  // advances them, so no copy of the original pointers stays live across it)
+  int64_t adv = 0;
   if constexpr (STEPS < 0) {
     // Long k: a loop over chunks of CH = -STEPS steps, each fully unrolled, with NB
     // buffers rotating across chunk boundaries (CH is a multiple of NB, so every chunk
     // starts on buffer 0); the tail after the last whole chunk drains with guarded loads.
+    // Steps are counted from the advanced pointers.
     constexpr int CH = -STEPS;
     static_assert(CH % NB == 0, "a chunk must hold whole rotations");
     uint64_t xa[NB][KV][RA], xb[NB][KV][RB];
@@ -291,16 +369,21 @@ __device__ __forceinline__ void tile(const uint64_t* __restrict__ A, int64_t lda
       for (; st + CH + NB - 1 <= full_steps; st += CH) {
 #pragma unroll
         for (int s = 0; s < CH; ++s) {
-          fetch(st + s + NB - 1, xa[(s + NB - 1) % NB], xb[(s + NB - 1) % NB]);
+          fetch(s + NB - 1, xa[(s + NB - 1) % NB], xb[(s + NB - 1) % NB]);
           __builtin_amdgcn_sched_barrier(0);
           compute(xa[s % NB], xb[s % NB]);
         }
+#pragma unroll
+        for (int f = 0; f < RA; ++f) arow[f] += CH * 2 * KV;
+#pragma unroll
+        for (int g = 0; g < RB; ++g) brow[g] += CH * 2 * KV;
       }
+      adv = st * 2 * KV;
 #pragma unroll
       for (int s = 0; s < CH + NB - 1; ++s) {
         if (st + s < full_steps) {
           if (st + s + NB - 1 < full_steps)
-            fetch(st + s + NB - 1, xa[(s + NB - 1) % NB], xb[(s + NB - 1) % NB]);
+            fetch(s + NB - 1, xa[(s + NB - 1) % NB], xb[(s + NB - 1) % NB]);
           __builtin_amdgcn_sched_barrier(0);
           compute(xa[s % NB], xb[s % NB]);
         }
@@ -333,9 +416,9 @@ tail:
         const int64_t wi = w + KV * half + v;
         uint64_t xa[RA], xb[RB];
 #pragma unroll
-        for (int f = 0; f < RA; ++f) xa[f] = wi < kw ? arow[f][w + v] : 0ull;
+        for (int f = 0; f < RA; ++f) xa[f] = wi < kw ? arow[f][w - adv + v] : 0ull;
 #pragma unroll
-        for (int g = 0; g < RB; ++g) xb[g] = wi < kw ? brow[g][w + v] : 0ull;
+        for (int g = 0; g < RB; ++g) xb[g] = wi < kw ? brow[g][w - adv + v] : 0ull;
         mfma_word<SEMI, RA, RB, FMT, WIDE>(xa, xb, acc);
       }
     }
@@ -361,53 +444,84 @@ constexpr int kLdsPanel = kLdsRows * kLdsRowB;     // bytes per stage buffer
 constexpr int kLdsChunks = kLdsRows * 4 / 256;     // 16-byte chunks per thread per stage
 constexpr int kLdsItemBytes = 2 * kLdsPanel;
 
-template <int SEMI, int FMT, bool WIDE>
-__device__ __forceinline__ void lds_item(const uint64_t* Ap, int64_t lda, const uint64_t* BTp,
+// A thread's share of an item's stage: chunk i is row (tid >> 2) + 64 i of the item's
+// 384 rows, words 2 (tid & 3) and 2 (tid & 3) + 1 of the stage.
+typedef uint64_t LdsStage[kLdsChunks][2];
+
+__device__ __forceinline__ void lds_sources(const uint64_t* Ap, int64_t lda, const uint64_t* BTp,
+                                            int64_t ldbt, int64_t m, int64_t n, int64_t im,
+                                            int64_t in, gq_ptr (&src)[kLdsChunks]) {
+  const int tid = threadIdx.x, part = tid & 3;
+  const int64_t row0 = im * 256, col0 = in * 128;
+#pragma unroll
+  for (int i = 0; i < kLdsChunks; ++i) {
+    const int r = (tid >> 2) + 64 * i;
+    if (r < 256) {
+      int64_t g = row0 + r;
+      g = g < m ? g : m - 1;
+      src[i] = (gq_ptr)Ap + g * lda + 2 * part;
+    } else {
+      int64_t g = col0 + (r - 256);
+      g = g < n ? g : n - 1;
+      src[i] = (gq_ptr)BTp + g * ldbt + 2 * part;
+    }
+  }
+}
+
+// Load the stage starting at word w0 (words at or past kw read as zero).
+__device__ __forceinline__ void lds_load(const gq_ptr (&src)[kLdsChunks], int64_t w0, int64_t kw,
+                                         bool aligned, LdsStage& stage) {
+  const int64_t wd = w0 + 2 * (threadIdx.x & 3);
+#pragma unroll
+  for (int i = 0; i < kLdsChunks; ++i) {
+    if (aligned && wd + 1 < kw) {
+      const ulonglong2 v = *reinterpret_cast<const ulonglong2*>((const uint64_t*)(src[i] + w0));
+      stage[i][0] = v.x;
+      stage[i][1] = v.y;
+    } else {
+      stage[i][0] = wd < kw ? src[i][w0] : 0ull;
+      stage[i][1] = wd + 1 < kw ? src[i][w0 + 1] : 0ull;
+    }
+  }
+}
+
+// The first stage of item (im, in), for a caller that overlaps it with other work.
+__device__ __forceinline__ void lds_prefetch(const uint64_t* Ap, int64_t lda, const uint64_t* BTp,
+                                             int64_t ldbt, int64_t m, int64_t k, int64_t n,
+                                             int64_t im, int64_t in, bool aligned,
+                                             LdsStage& stage) {
+  gq_ptr src[kLdsChunks];
+  lds_sources(Ap, lda, BTp, ldbt, m, n, im, in, src);
+  lds_load(src, 0, (k + 63) >> 6, aligned, stage);
+}
+
+struct LdsNoNext {
+  __device__ void operator()() const {}
+  __device__ bool operator()(LdsStage&) const { return false; }
+};
+
+// preloaded: `stage` already holds the item's first stage (lds_prefetch).  at_last()
+// runs on every wave just before the barrier that ends the last stage (a persistent
+// caller's wave 0 names the next item there); after that barrier, before the epilogue,
+// prefetch(stage) may load the next item's first stage into `stage` and returns whether
+// it did, which lds_item returns.
+template <int SEMI, int FMT, bool WIDE, class AtLast = LdsNoNext, class Prefetch = LdsNoNext>
+__device__ __forceinline__ bool lds_item(const uint64_t* Ap, int64_t lda, const uint64_t* BTp,
                                          int64_t ldbt, uint64_t* C, int64_t ldc, int64_t m,
                                          int64_t k, int64_t n, int64_t im, int64_t in,
                                          int64_t tiles_m, int64_t tiles_n, bool aligned,
                                          int accumulate, int semiring, int w,
-                                         unsigned char* smem) {
+                                         unsigned char* smem, LdsStage& stage,
+                                         bool preloaded = false, AtLast at_last = AtLast(),
+                                         Prefetch prefetch = Prefetch()) {
   constexpr int RA = 4, RB = 2;
   const int tid = threadIdx.x, lane = tid & 63, half = lane >> 5, li = lane & 31;
-  const int64_t row0 = im * 256, col0 = in * 128;
-  const gq_ptr A = (gq_ptr)Ap;
-  const gq_ptr BT = (gq_ptr)BTp;
   const int64_t kw = (k + 63) >> 6;
-  // staging: chunk q = tid + 256 i covers row q >> 2, words 2 (q & 3) .. + 1 of a stage
   gq_ptr src[kLdsChunks];
-  int soff[kLdsChunks], spart[kLdsChunks];
+  lds_sources(Ap, lda, BTp, ldbt, m, n, im, in, src);
+  int soff[kLdsChunks];
 #pragma unroll
-  for (int i = 0; i < kLdsChunks; ++i) {
-    const int q = tid + 256 * i;
-    const int r = q >> 2, part = q & 3;
-    spart[i] = part;
-    if (r < 256) {
-      int64_t g = row0 + r;
-      g = g < m ? g : m - 1;
-      src[i] = A + g * lda + 2 * part;
-    } else {
-      int64_t g = col0 + (r - 256);
-      g = g < n ? g : n - 1;
-      src[i] = BT + g * ldbt + 2 * part;
-    }
-    soff[i] = r * kLdsRowB + part * 16;
-  }
-  uint64_t stage[kLdsChunks][2];
-  auto load = [&](int64_t w0) {
-#pragma unroll
-    for (int i = 0; i < kLdsChunks; ++i) {
-      const int64_t wd = w0 + 2 * spart[i];
-      if (aligned && wd + 1 < kw) {
-        const ulonglong2 v = *reinterpret_cast<const ulonglong2*>((const uint64_t*)(src[i] + w0));
-        stage[i][0] = v.x;
-        stage[i][1] = v.y;
-      } else {
-        stage[i][0] = wd < kw ? src[i][w0] : 0ull;
-        stage[i][1] = wd + 1 < kw ? src[i][w0 + 1] : 0ull;
-      }
-    }
-  };
+  for (int i = 0; i < kLdsChunks; ++i) soff[i] = ((tid >> 2) + 64 * i) * kLdsRowB + (tid & 3) * 16;
   auto store = [&](int buf) {
 #pragma unroll
     for (int i = 0; i < kLdsChunks; ++i) {
@@ -431,12 +545,16 @@ __device__ __forceinline__ void lds_item(const uint64_t* Ap, int64_t lda, const 
   for (int g = 0; g < RB; ++g) boff[g] = (256 + wx * 64 + 32 * g + li) * kLdsRowB + 16 * half;
 
   const int64_t stages = (kw + kLdsKs - 1) / kLdsKs;
-  load(0);
+  if (!preloaded) lds_load(src, 0, kw, aligned, stage);
   store(0);
   __syncthreads();
+  if (stages == 0) {
+    at_last();
+    __syncthreads();
+  }
   for (int64_t st = 0; st < stages; ++st) {
     const int cur = (int)(st & 1);
-    if (st + 1 < stages) load((st + 1) * kLdsKs);
+    if (st + 1 < stages) lds_load(src, (st + 1) * kLdsKs, kw, aligned, stage);
     const unsigned char* base = smem + cur * kLdsPanel;
     // two groups of 4 words per stage: lane half h takes words 4s + 2h and 4s + 2h + 1
 #pragma unroll
@@ -458,12 +576,19 @@ __device__ __forceinline__ void lds_item(const uint64_t* Ap, int64_t lda, const 
       mfma_word<SEMI, RA, RB, FMT, WIDE>(xa[0], xb[0], acc);
       mfma_word<SEMI, RA, RB, FMT, WIDE>(xa[1], xb[1], acc);
     }
-    if (st + 1 < stages) store(cur ^ 1);
+    if (st + 1 < stages)
+      store(cur ^ 1);
+    else
+      at_last();
     __syncthreads();
   }
+  // no wave reads this item's LDS panels any more: the next item's first stage can be
+  // in flight during the epilogue
+  const bool next = prefetch(stage);
   const int64_t tm = 2 * im + wy, tn = 2 * in + wx;
   if (tm < tiles_m && tn < tiles_n)
     epilogue<SEMI, RA, RB, FMT>(acc, C, ldc, m, n, tm, tn, accumulate, semiring);
+  return next;
 }
 
 }  // namespace mfma

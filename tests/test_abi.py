@@ -3,6 +3,7 @@ include/bmm.h declares, and rejects bad arguments before touching a GPU."""
 import ctypes
 import os
 import re
+import subprocess
 
 import pytest
 
@@ -149,6 +150,43 @@ def test_leaf_tiles_and_status_strings():
     assert bmm.bmm_leaf_tile_shape(bmm.LEAF_MFMA_I8, 8) == (256, 128)  # LDS-shared 2 x 2 waves
     assert bmm.bmm_leaf_tile_shape(bmm.LEAF_VALU, 1) == (128, 128)
     assert "gfx950" in bmm.bmm_version()
+
+
+def test_options_layout_matches_header(tmp_path):
+    """The binding's Options mirrors bmm_options field for field (a C program built
+    against include/bmm.h prints the size and offsets)."""
+    import paper_1909_01554_amd as bmm
+    names = [f for f, _ in bmm.Options._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stddef.h>\n#include <stdio.h>\n#include "bmm.h"\n'
+                   'int main(void) {\n  printf("%zu", sizeof(bmm_options));\n' +
+                   "".join(f'  printf(" %zu", offsetof(bmm_options, {f}));\n' for f in names) +
+                   '  printf("\\n");\n  return 0;\n}\n')
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True,
+                                          check=True).stdout.split()]
+    want = [ctypes.sizeof(bmm.Options)] + [getattr(bmm.Options, f).offset for f in names]
+    assert got == want
+
+
+def test_k_panel_table_roundtrip(tmp_path):
+    """k-panel records load, save and reject malformed lines (panel not a whole number of
+    words, unknown semiring)."""
+    import paper_1909_01554_amd as bmm
+    p = tmp_path / "kp.txt"
+    p.write_text("kpanel 1 4096 65536 4096 16384\n")
+    bmm.bmm_autotune_load(str(p))
+    q = tmp_path / "out.txt"
+    bmm.bmm_autotune_save(str(q))
+    assert "kpanel 1 4096 65536 4096 16384" in q.read_text()
+    for bad in ["kpanel 1 4096 65536 4096 1000\n", "kpanel 5 64 64 64 64\n",
+                "kpanel 0 64 0 64 64\n"]:
+        p.write_text(bad)
+        with pytest.raises(bmm.BmmError):
+            bmm.bmm_autotune_load(str(p))
+    assert bmm.Options().k_panel == 0
 
 
 def test_autotune_table_roundtrip(tmp_path):

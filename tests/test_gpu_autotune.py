@@ -32,6 +32,33 @@ def test_autotuned_cubic_leaf_is_exact(bmm, sr):
     assert np.array_equal(from_dev(Cd), oracle.mul(A, B, k, n, sr))
 
 
+@pytest.mark.parametrize("sr", [oracle.GF2, oracle.BOOLEAN])
+def test_k_panel_tuner(bmm, sr, tmp_path):
+    """The k-panel tuner picks one of the candidates, leaves the product in C, records
+    its choice for k_panel = 0 (the product that uses it stays exact) and refuses
+    accumulation."""
+    m, k, n = 256, 16384, 320
+    A = bmmgen.fill_cpu(m, k, 9, bmmgen.TAG_A, bmmgen.Dist.half())
+    B = bmmgen.fill_cpu(k, n, 9, bmmgen.TAG_B, bmmgen.Dist.half())
+    want = oracle.mul(A, B, k, n, sr)
+    Ad, Bd = to_dev(A), to_dev(B)
+    Cd = empty_dev(m, words(n), fill=-1)
+    announce("k-panel tuner", sr)
+    bits, secs = bmm.bmm_autotune_k_panel(sr, Ad, Bd, Cd, m, k, n, candidates=[k, 4096, 1000])
+    assert bits in (k, 4096, 1024) and secs > 0
+    assert np.array_equal(from_dev(Cd), want)
+    p = tmp_path / "t.txt"
+    bmm.bmm_autotune_save(str(p))
+    assert f"kpanel {sr} {m} {k} {n} {bits}" in p.read_text()
+    Cd = empty_dev(m, words(n), fill=-1)
+    fn = bmm.bmm_gf2 if sr == oracle.GF2 else bmm.bmm_boolean
+    fn(Ad, Bd, Cd, m, k, n)
+    assert np.array_equal(from_dev(Cd), want)
+    with pytest.raises(bmm.BmmError):
+        bmm.bmm_autotune_k_panel(sr, Ad, Bd, Cd, m, k, n,
+                                 options=bmm.Options(flags=bmm.FLAG_ACCUMULATE))
+
+
 def test_autotuned_strassen_depth_is_exact(bmm, tmp_path):
     import torch
     n = 4096

@@ -29,8 +29,8 @@ def gen(rows, cols, seed, tag, p=None):
     return bmmgen.fill_cpu(rows, cols, seed, tag, dist)
 
 
-def run(bmm, sr, leaf, tile, A, B, m, k, n, b_t=False, acc_init=None, pad=0):
-    opts = bmm.Options(leaf=leaf, tile=tile)
+def run(bmm, sr, leaf, tile, A, B, m, k, n, b_t=False, acc_init=None, pad=0, k_panel=0):
+    opts = bmm.Options(leaf=leaf, tile=tile, k_panel=k_panel)
     Ad = to_dev(A, A.shape[1] + pad)
     if b_t:
         BT = oracle_transpose(B, k, n)
@@ -86,8 +86,11 @@ def test_ragged_shapes(bmm, sname, sr, lname, leaf, tile):
 
 
 @pytest.mark.parametrize("sname,sr", SEMIRINGS)
-@pytest.mark.parametrize("lname,leaf,tile", LEAVES[:3])
+@pytest.mark.parametrize("lname,leaf,tile", LEAVES)
 def test_transposed_b_and_accumulate(bmm, sname, sr, lname, leaf, tile):
+    """B passed transposed, and C accumulated into, with odd and even C pitches (5 and 6
+    words: the 128-column tiles store 16-byte pieces only where a row starts 16-byte
+    aligned, and the last tile's single word alone)."""
     m, k, n = 200, 777, 300
     A = gen(m, k, 5, bmmgen.TAG_A)
     B = gen(k, n, 5, bmmgen.TAG_B)
@@ -95,9 +98,36 @@ def test_transposed_b_and_accumulate(bmm, sname, sr, lname, leaf, tile):
     want = oracle.mul(A, B, k, n, sr)
     announce("b_t", sname, lname)
     assert np.array_equal(run(bmm, sr, leaf, tile, A, B, m, k, n, b_t=True), want)
-    announce("accumulate", sname, lname)
-    got = run(bmm, sr, leaf, tile, A, B, m, k, n, acc_init=C0)
-    assert np.array_equal(got, (want ^ C0) if sr == oracle.GF2 else (want | C0))
+    for pad in (0, 1):
+        announce("accumulate", sname, lname, pad)
+        got = run(bmm, sr, leaf, tile, A, B, m, k, n, acc_init=C0, pad=pad)
+        assert np.array_equal(got, (want ^ C0) if sr == oracle.GF2 else (want | C0))
+
+
+# (m, k, n, panel bits): one-word panels, odd-word panels (8-byte loads after the
+# first), the recursion's 2048-bit panels, a panel rounded up to whole words (3000 ->
+# 3008), and a ragged last panel
+KPANEL = [(64, 300, 130, 64), (100, 1000, 70, 128), (130, 4096, 200, 2048),
+          (70, 777, 300, 192), (33, 8192, 65, 3000), (200, 5000, 128, 4096)]
+
+
+@pytest.mark.parametrize("sname,sr", SEMIRINGS)
+@pytest.mark.parametrize("lname,leaf,tile", [LEAVES[0], LEAVES[1], LEAVES[7], LEAVES[9],
+                                             LEAVES[8], LEAVES[6]])
+def test_k_panels(bmm, sname, sr, lname, leaf, tile):
+    """C as the sum of panel products over k (each panel's product XORed / ORed into C
+    after the first), fresh and accumulated, against the oracle's plain product."""
+    for i, (m, k, n, kp) in enumerate(KPANEL):
+        p = None if sr == oracle.GF2 else bmmgen.Dist.inv_sqrt(k)
+        A = gen(m, k, 31 + i, bmmgen.TAG_A, p)
+        B = gen(k, n, 31 + i, bmmgen.TAG_B, p)
+        want = oracle.mul(A, B, k, n, sr)
+        announce("k panels", sname, lname, (m, k, n, kp))
+        assert np.array_equal(run(bmm, sr, leaf, tile, A, B, m, k, n, k_panel=kp,
+                                  b_t=i % 2 == 1), want), (m, k, n, kp)
+        C0 = gen(m, n, 31 + i, 0xC0)
+        got = run(bmm, sr, leaf, tile, A, B, m, k, n, acc_init=C0, k_panel=kp)
+        assert np.array_equal(got, (want ^ C0) if sr == oracle.GF2 else (want | C0)), kp
 
 
 def test_k_zero_and_empty(bmm):
