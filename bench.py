@@ -29,12 +29,14 @@ PEAK_MFMA_F4_TOPS = 10100.0       # dense fp4 (E2M1) MFMA
 #    calibration kernel (bmm_calibrate_valu, bench --mode valu) measures.
 PEAK_VALU_SINGLE_TBOPS = 2516.6
 PEAK_VALU_FUSED_TBOPS = 5033.2
-# Bytes that one Boolean leaf launch at n = 2^18 moves between L2 and memory: rocprofv3
-# FETCH_SIZE and WRITE_SIZE of the int8 leaf with the tuned tile (7: 64 x 128, chunked
-# loop, wide operand expansion), scaled by the same counters on a 4 GiB copy in the same
-# runs (reads x 2.0, writes x 1.0); see profiles/pmc_traffic_leaf_boolean_n262144.md.
-# Valid for that kernel only.
-MEASURED_TRAFFIC = {("mfma", 7, 1 << 18): (1.1294e10 * 2.0 + 6.88363e7) * 1024}
+# Bytes that one Boolean leaf launch at n = 2^18 (sparse operands) moves between L2 and
+# memory, for the int8 leaf with the tuned tile (7: 64 x 128, chunked loop, wide operand
+# expansion, 16-byte C stores): reads from rocprofv3's request counts by size (128 x
+# TCC_EA0_RDREQ_128B + 64 x TCC_EA0_RDREQ_64B; FETCH_SIZE counts a 128-byte read as 64
+# bytes on this device, which a 4 GiB copy in the same runs shows), writes from
+# WRITE_SIZE (the copy's 4 GiB read back exactly); see
+# profiles/pmc_traffic_leaf_boolean_n262144.md.  Valid for that kernel only.
+MEASURED_TRAFFIC = {("mfma", 7, 1 << 18): 1.76381e11 * 128 + 3.14568e7 * 64 + 1.37406e7 * 1024}
 
 
 def log(*a):
