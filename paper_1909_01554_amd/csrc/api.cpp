@@ -256,40 +256,52 @@ int cubic_product(int semiring, const uint64_t* A, int64_t lda, const uint64_t* 
   BMM_TRY(validate_product(A, lda, B, ldb, C, ldc, m, k, n, b_t));
   if (m == 0 || n == 0) return BMM_OK;
   const bool acc = (o.flags & BMM_FLAG_ACCUMULATE) != 0;
-  const int64_t kw = words_of(k);
-  const size_t bt_bytes = (size_t)n * kw * 8;
-  if (caller_bt && k > 0 && !b_t && bt_bytes > caller_bt->bytes)
-    return fail(BMM_E_UNSUPPORTED,
-                "B^T needs %zu bytes of scratch and this entry point has %zu: pass B "
-                "transposed (BMM_FLAG_B_TRANSPOSED) or call bmm_gf2 / bmm_boolean",
-                bt_bytes, caller_bt->bytes);
-  void* buf = nullptr;
-  if (caller_bt && k > 0 && !b_t) {
-    BMM_TRY(caller_bt->get(&buf));
-  }
   hipStream_t s = (hipStream_t)stream;
   if (k == 0) {
     if (!acc) HIP_TRY(launch_zero(C, ldc, m, words_of(n), s), "zero");
     return BMM_OK;
   }
-  const uint64_t* BT = B;
-  int64_t ldbt = ldb;
-  if (!b_t) {
-    if (!buf) BMM_TRY(scratch(bt_bytes, &buf));
-    HIP_TRY(launch_transpose(B, ldb, 0, (uint64_t*)buf, kw, 0, k, n, 1, s), "transpose");
-    BT = (const uint64_t*)buf;
-    ldbt = kw;
-  }
   int leaf, tile;
   pick_leaf(semiring, m, k, n, 1, o, &leaf, &tile);
+  // The VALU leaf's outer-product form (tile 2) reads B row-major; every other leaf reads
+  // B^T. Whichever form the leaf needs and the caller did not pass is staged in scratch.
+  const bool outer = leaf == BMM_LEAF_VALU && tile == 2;
+  const int64_t kw = words_of(k), nw = words_of(n);
+  const bool stage = outer ? b_t : !b_t;
+  const size_t stage_bytes = outer ? (size_t)k * nw * 8 : (size_t)n * kw * 8;
+  if (caller_bt && stage && stage_bytes > caller_bt->bytes)
+    return fail(BMM_E_UNSUPPORTED,
+                "staging B for this leaf needs %zu bytes of scratch and this entry point has "
+                "%zu: pass B in the form the leaf reads (B^T for the MFMA leaves and VALU tile "
+                "1, B for VALU tile 2) or call bmm_gf2 / bmm_boolean",
+                stage_bytes, caller_bt->bytes);
+  const uint64_t* Bl = B;  // B^T, or B for the outer-product form
+  int64_t ldl = ldb;
+  if (stage) {
+    void* buf = nullptr;
+    if (caller_bt) BMM_TRY(caller_bt->get(&buf));
+    else BMM_TRY(scratch(stage_bytes, &buf));
+    if (outer)  // B^T (n x k) -> B (k x n)
+      HIP_TRY(launch_transpose(B, ldb, 0, (uint64_t*)buf, nw, 0, n, k, 1, s), "transpose");
+    else        // B (k x n) -> B^T (n x k)
+      HIP_TRY(launch_transpose(B, ldb, 0, (uint64_t*)buf, kw, 0, k, n, 1, s), "transpose");
+    Bl = (const uint64_t*)buf;
+    ldl = outer ? nw : kw;
+  }
   // k in panels: C = sum over panels of A[:, panel] B[panel, :], each panel's product
   // added into C (XOR or OR) after the first; the leaf and tile are the full shape's
   const int64_t panel = k_panel_bits(semiring, m, k, n, o);
   for (int64_t p0 = 0; p0 < k; p0 += panel) {
     const int64_t kp = std::min(panel, k - p0);
-    LeafBatch p{A + p0 / 64, lda, 0, BT + p0 / 64, ldbt, 0, C, ldc, 0, m, kp, n, 1,
-                (acc || p0 > 0) ? 1 : 0};
-    BMM_TRY(run_leaf(semiring, leaf, tile, p, s));
+    const int pacc = (acc || p0 > 0) ? 1 : 0;
+    if (outer) {
+      HIP_TRY(launch_leaf_valu_outer(semiring, A + p0 / 64, lda, Bl + p0 * ldl, ldl, C, ldc, m,
+                                     kp, n, pacc, s),
+              "leaf launch");
+    } else {
+      LeafBatch p{A + p0 / 64, lda, 0, Bl + p0 / 64, ldl, 0, C, ldc, 0, m, kp, n, 1, pacc};
+      BMM_TRY(run_leaf(semiring, leaf, tile, p, s));
+    }
   }
   return BMM_OK;
 }
@@ -880,7 +892,7 @@ int bmm_compress(int levels, int scheme, const uint64_t* src, uint64_t* dst, int
 
 int bmm_leaf_tiles(int leaf, int* count_out) {
   if (!count_out) return fail(BMM_E_INVAL, "null count_out");
-  if (leaf == BMM_LEAF_VALU) *count_out = 1;
+  if (leaf == BMM_LEAF_VALU) *count_out = 2;
   else if (leaf == BMM_LEAF_MFMA_I8 || leaf == BMM_LEAF_MFMA_F4) *count_out = MFMA_NUM_TILES;
   else return fail(BMM_E_INVAL, "unknown leaf %d", leaf);
   return BMM_OK;
@@ -897,9 +909,9 @@ int bmm_leaf_choice(int semiring, int64_t m, int64_t k, int64_t n, int64_t batch
 
 int bmm_leaf_tile_shape(int leaf, int tile, int* rows_out, int* cols_out) {
   if (!rows_out || !cols_out) return fail(BMM_E_INVAL, "null output");
-  if (leaf == BMM_LEAF_VALU && tile == 1) {
-    *rows_out = 128;
-    *cols_out = 128;
+  if (leaf == BMM_LEAF_VALU && (tile == 1 || tile == 2)) {
+    *rows_out = tile == 1 ? 128 : 512;
+    *cols_out = tile == 1 ? 128 : 1024;
     return BMM_OK;
   }
   if ((leaf == BMM_LEAF_MFMA_I8 || leaf == BMM_LEAF_MFMA_F4) && tile >= 1 &&
@@ -932,7 +944,10 @@ int bmm_autotune_leaf(int semiring, int64_t m, int64_t k, int64_t n, int64_t bat
   const int64_t kw = words_of(k), nw = words_of(n);
   const int64_t nb = batch_bucket(batch);  // time on the bucket's batch size
   uint64_t *A = nullptr, *BT = nullptr, *C = nullptr;
-  const size_t ba = (size_t)m * kw * 8, bb = (size_t)n * kw * 8, bc = (size_t)m * nw * 8;
+  // the right operand buffer serves as B^T (n x k) and, for the VALU leaf's
+  // outer-product form, as B (k x n)
+  const size_t ba = (size_t)m * kw * 8, bb = (size_t)std::max(n * kw, k * nw) * 8,
+               bc = (size_t)m * nw * 8;
   if (dev_malloc((void**)&A, ba * nb) != hipSuccess || dev_malloc((void**)&BT, bb * nb) != hipSuccess ||
       dev_malloc((void**)&C, bc * nb) != hipSuccess) {
     (void)hipGetLastError();
@@ -954,15 +969,22 @@ int bmm_autotune_leaf(int semiring, int64_t m, int64_t k, int64_t n, int64_t bat
   if (rc == BMM_OK)
     rc = check_hip(launch_random(BT, (int64_t)(bb * nb / 8), 0x5EED0002ull, nullptr), "tuning data");
   std::vector<std::pair<int, int>> cands = {{BMM_LEAF_VALU, 1}};
+  if (nb == 1) cands.push_back({BMM_LEAF_VALU, 2});  // cubic products only
   for (int t = 1; t <= MFMA_NUM_TILES; ++t) cands.push_back({BMM_LEAF_MFMA_I8, t});
   if (k < ((int64_t)1 << 24))
     for (int t = 1; t <= MFMA_NUM_TILES; ++t) cands.push_back({BMM_LEAF_MFMA_F4, t});
   for (auto [leaf, tile] : cands) {
     if (rc != BMM_OK) break;
     LeafBatch p{A, kw, m * kw, BT, kw, n * kw, C, nw, m * nw, m, k, n, nb, 0};
+    auto launch = [&, leaf = leaf, tile = tile]() {
+      if (leaf == BMM_LEAF_VALU && tile == 2)
+        return check_hip(launch_leaf_valu_outer(semiring, A, kw, BT, nw, C, nw, m, k, n, 0,
+                                                nullptr), "leaf launch");
+      return run_leaf(semiring, leaf, tile, p, nullptr);
+    };
     // a timed warm-up; launches longer than 0.2 s are timed once, shorter ones 3 more times
     (void)hipEventRecord(e0, nullptr);
-    rc = run_leaf(semiring, leaf, tile, p, nullptr);
+    rc = launch();
     (void)hipEventRecord(e1, nullptr);
     if (rc != BMM_OK) break;
     if (hipEventSynchronize(e1) != hipSuccess) {
@@ -975,8 +997,7 @@ int bmm_autotune_leaf(int semiring, int64_t m, int64_t k, int64_t n, int64_t bat
     if (ms < 200.f) {
       reps = 3;
       (void)hipEventRecord(e0, nullptr);
-      for (int r = 0; r < reps && rc == BMM_OK; ++r)
-        rc = run_leaf(semiring, leaf, tile, p, nullptr);
+      for (int r = 0; r < reps && rc == BMM_OK; ++r) rc = launch();
       (void)hipEventRecord(e1, nullptr);
       if (rc != BMM_OK) break;
       if (hipEventSynchronize(e1) != hipSuccess) {
@@ -1204,7 +1225,7 @@ int bmm_autotune_load(const char* path) {
                &leaf, &t1, &t2, &t3) == 9) {
       int cnt = 0;
       if ((sr != BMM_GF2 && sr != BMM_BOOLEAN) || m <= 0 || n <= 0 || k < 0 || b <= 0 ||
-          leaf < 1 || leaf > 3 || t1 < 0 || t1 > 1 || t2 < 0 || t3 < 0 ||
+          leaf < 1 || leaf > 3 || t1 < 0 || t1 > 2 || t2 < 0 || t3 < 0 ||
           bmm_leaf_tiles(BMM_LEAF_MFMA_I8, &cnt) != BMM_OK || t2 > cnt || t3 > cnt)
         return fail(BMM_E_INVAL, "bad leaf line: %s", line.c_str());
       std::lock_guard<std::mutex> lock(g_mu);

@@ -92,6 +92,12 @@ hipError_t launch_leaf_mfma_f4(int semiring, const LeafBatch& p, int tile, hipSt
 // The 8-wave workgroup variant that shares operand panels through LDS (fmt 0: int8, 1: fp4).
 hipError_t launch_leaf_mfma_lds(int semiring, int fmt, const LeafBatch& p, hipStream_t s);
 hipError_t launch_leaf_valu(int semiring, const LeafBatch& p, int tile, hipStream_t s);
+// The VALU leaf in outer-product form (tile 2): B row-major (k x n, pitch ldb words), one
+// product; k = 0 leaves C zero (or unchanged when accumulating).
+hipError_t launch_leaf_valu_outer(int semiring, const uint64_t* A, int64_t lda,
+                                  const uint64_t* B, int64_t ldb, uint64_t* C, int64_t ldc,
+                                  int64_t m, int64_t k, int64_t n, int accumulate,
+                                  hipStream_t s);
 // The last recursion level shifted into the int8 leaf (leaf_shift.hip): for every
 // parent p, the seven child products of its quadrants (alpha, beta of `scheme`) are
 // formed, multiplied and combined by gamma into the parent's result quadrants.

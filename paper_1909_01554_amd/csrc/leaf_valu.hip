@@ -149,6 +149,126 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void l
   }
 }
 
+// Outer-product form (tile 2), for cubic products whose B is at hand row-major: every
+// bit A[i][j] selects row j of B, C[i][.] ^= (A[i][j] ? B[j][.] : 0) (GF(2)) or |=
+// (Boolean), 32 columns per v_bitop3_b32 with the selection as a sign-extended mask.  A
+// wave owns 256 rows (four per lane) and 512 columns (16 dwords) of C; the words of row j
+// of B that the wave needs are the same for all its lanes, so they are read with scalar
+// loads into scalar registers and each fold reads one vector register besides its
+// accumulator (no LDS).  The accumulators are the result bits themselves: no reduction.
+// The four waves of a workgroup own 1024 rows over the same columns, so they read the
+// same rows of B (scalar cache hits).  Scalar loads may complete out of order, so a use
+// waits for every one in flight: row j + 1 is requested right after row j's first use,
+// and its latency hides behind the rest of row j's folds and the other waves of the SIMD.
+constexpr int OROWS = 4;             // rows per lane
+constexpr int OCW = 16;              // C dwords (32 columns each) per wave
+constexpr int OTM = 4 * 64 * OROWS;  // rows per workgroup
+constexpr int OTN = 32 * OCW;        // columns per workgroup
+
+template <bool FULL>
+__device__ __forceinline__ void outer_row(const uint32_t* __restrict__ r, int ncw,
+                                          uint32_t (&bw)[OCW]) {
+#pragma unroll
+  for (int c = 0; c < OCW; ++c) bw[c] = (FULL || c < ncw) ? r[c] : 0u;
+}
+
+// The steps of one k-dword a of A (min(left, 32) bits; left > 0): cur holds row j of B on
+// entry and row j + 32 (or nothing past k) on exit; brow points at row j and advances.
+template <int SEMI, bool FULL>
+__device__ __forceinline__ void outer_dword(const uint32_t*& brow, int64_t ldb32, int64_t left,
+                                            int ncw, const uint32_t (&a)[OROWS],
+                                            uint32_t (&cur)[OCW], uint32_t (&acc)[OROWS][OCW]) {
+  const int nsteps = (int)(left < 32 ? left : 32);
+  for (int jb = 0; jb < nsteps; ++jb) {
+    uint32_t msk[OROWS];
+#pragma unroll
+    for (int r = 0; r < OROWS; ++r) msk[r] = (uint32_t)__builtin_amdgcn_sbfe((int)a[r], jb, 1);
+#pragma unroll
+    for (int r = 0; r < OROWS; ++r) acc[r][0] = fold<SEMI>(msk[r], cur[0], acc[r][0]);
+    __builtin_amdgcn_sched_barrier(0);
+    brow += ldb32;
+    uint32_t nxt[OCW];
+    if (jb + 1 < left) outer_row<FULL>(brow, ncw, nxt);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int q = 1; q < OCW; ++q)
+#pragma unroll
+      for (int r = 0; r < OROWS; ++r) acc[r][q] = fold<SEMI>(msk[r], cur[q], acc[r][q]);
+#pragma unroll
+    for (int q = 0; q < OCW; ++q) cur[q] = nxt[q];
+  }
+}
+
+// FULL: the rows of B and C hold at least OCW dwords, so every wave reads a whole window
+// of OCW dwords of row j (the last column tile's window is moved left to end at the row's
+// end, and that wave stores only the columns of its own tile); otherwise (n < 512) the
+// loads past the row read zero.
+template <int SEMI, bool FULL>
+__global__ __launch_bounds__(256) void leaf_valu_outer_kernel(
+    const uint64_t* __restrict__ A, int64_t lda, const uint32_t* __restrict__ B, int64_t ldb32,
+    uint64_t* __restrict__ C, int64_t ldc, int64_t m, int64_t k, int64_t n, int64_t tiles_m,
+    int64_t tiles_n, int accumulate) {
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const TileCoord c = xcd_tile(blockIdx.x, gridDim.x, tiles_m, tiles_n);
+  const int64_t row0 = c.tm * OTM + wave * (64 * OROWS);
+  const int64_t n32 = ((n + 63) >> 6) * 2;  // dwords per row of B and C (whole words)
+  const int64_t own32 = c.tn * OCW;         // first C dword of the wave's own columns
+  // first dword of the window the wave computes
+  const int64_t col32 = FULL ? (own32 + OCW <= n32 ? own32 : n32 - OCW) : own32;
+  const int ncw = (int)(n32 - col32 < OCW ? n32 - col32 : OCW);
+  int64_t ri[OROWS];
+  const uint32_t* arow[OROWS];
+#pragma unroll
+  for (int r = 0; r < OROWS; ++r) {
+    ri[r] = row0 + 64 * r + lane;
+    const int64_t g = ri[r] < m ? ri[r] : m - 1;
+    arow[r] = reinterpret_cast<const uint32_t*>(A + g * lda);
+  }
+  uint32_t acc[OROWS][OCW];
+#pragma unroll
+  for (int r = 0; r < OROWS; ++r)
+#pragma unroll
+    for (int q = 0; q < OCW; ++q) acc[r][q] = 0u;
+  // One step per bit j of k (outer_dword), 32 per k-dword of A. The k-dwords of A
+  // alternate between two register sets, each loaded a whole k-dword ahead of its use
+  // (the last one is reread rather than skipped, so no copy waits for a load).
+  const int64_t k32 = (k + 31) >> 5;  // k-dwords of A
+  const uint32_t* brow = B + col32;
+  uint32_t a0[OROWS], a1[OROWS], cur[OCW];
+#pragma unroll
+  for (int r = 0; r < OROWS; ++r) a0[r] = arow[r][0];
+  outer_row<FULL>(brow, ncw, cur);
+  for (int64_t jw = 0; jw < k32; jw += 2) {
+    const int64_t j1 = jw + 1 < k32 ? jw + 1 : k32 - 1;
+#pragma unroll
+    for (int r = 0; r < OROWS; ++r) a1[r] = arow[r][j1];
+    outer_dword<SEMI, FULL>(brow, ldb32, k - 32 * jw, ncw, a0, cur, acc);
+    if (jw + 1 >= k32) break;
+    const int64_t j2 = jw + 2 < k32 ? jw + 2 : k32 - 1;
+#pragma unroll
+    for (int r = 0; r < OROWS; ++r) a0[r] = arow[r][j2];
+    outer_dword<SEMI, FULL>(brow, ldb32, k - 32 * (jw + 1), ncw, a1, cur, acc);
+  }
+  // the accumulators are C's dwords: two make a 64-bit word of the row
+  const int64_t nw = n32 >> 1, w0 = col32 >> 1, own = own32 >> 1;
+#pragma unroll
+  for (int r = 0; r < OROWS; ++r) {
+    if (ri[r] >= m) continue;
+    uint64_t* dst = C + ri[r] * ldc + w0;
+#pragma unroll
+    for (int w = 0; w < OCW / 2; ++w) {
+      if (w0 + w >= nw) break;  // uniform
+      if (w0 + w < own) continue;  // uniform: the previous tile's columns
+      uint64_t x = (uint64_t)acc[r][2 * w] | ((uint64_t)acc[r][2 * w + 1] << 32);
+      const int64_t c0 = (w0 + w) * 64;
+      if (n - c0 < 64) x &= (1ull << (n - c0)) - 1ull;  // padding columns stay zero
+      if (accumulate) x = (SEMI == GF2) ? (x ^ dst[w]) : (x | dst[w]);
+      dst[w] = x;
+    }
+  }
+}
+
 }  // namespace
 
 hipError_t launch_leaf_valu(int semiring, const LeafBatch& p, int /*tile*/, hipStream_t s) {
@@ -163,6 +283,36 @@ hipError_t launch_leaf_valu(int semiring, const LeafBatch& p, int /*tile*/, hipS
   else
     hipLaunchKernelGGL(leaf_valu_kernel<BOOLEAN>, dim3((unsigned)blocks), dim3(256), 0, s, p,
                        tiles_m, tiles_n);
+  return hipGetLastError();
+}
+
+hipError_t launch_leaf_valu_outer(int semiring, const uint64_t* A, int64_t lda,
+                                  const uint64_t* B, int64_t ldb, uint64_t* C, int64_t ldc,
+                                  int64_t m, int64_t k, int64_t n, int accumulate,
+                                  hipStream_t s) {
+  if (m <= 0 || n <= 0) return hipSuccess;
+  const int64_t tiles_m = (m + OTM - 1) / OTM;
+  const int64_t tiles_n = (((n + 63) / 64) * 64 + OTN - 1) / OTN;
+  const int64_t blocks = tiles_m * tiles_n;
+  if (!grid_fits(blocks, 256)) return kGridTooLarge;
+  const uint32_t* B32 = reinterpret_cast<const uint32_t*>(B);
+  const bool full = ((n + 63) / 64) * 2 >= OCW;
+  const dim3 g((unsigned)blocks), b(256);
+  if (semiring == GF2) {
+    if (full)
+      hipLaunchKernelGGL((leaf_valu_outer_kernel<GF2, true>), g, b, 0, s, A, lda, B32, 2 * ldb,
+                         C, ldc, m, k, n, tiles_m, tiles_n, accumulate);
+    else
+      hipLaunchKernelGGL((leaf_valu_outer_kernel<GF2, false>), g, b, 0, s, A, lda, B32, 2 * ldb,
+                         C, ldc, m, k, n, tiles_m, tiles_n, accumulate);
+  } else {
+    if (full)
+      hipLaunchKernelGGL((leaf_valu_outer_kernel<BOOLEAN, true>), g, b, 0, s, A, lda, B32,
+                         2 * ldb, C, ldc, m, k, n, tiles_m, tiles_n, accumulate);
+    else
+      hipLaunchKernelGGL((leaf_valu_outer_kernel<BOOLEAN, false>), g, b, 0, s, A, lda, B32,
+                         2 * ldb, C, ldc, m, k, n, tiles_m, tiles_n, accumulate);
+  }
   return hipGetLastError();
 }
 

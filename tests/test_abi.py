@@ -140,7 +140,7 @@ def test_workspace_formula():
 
 def test_leaf_tiles_and_status_strings():
     import paper_1909_01554_amd as bmm
-    assert bmm.bmm_leaf_tiles(bmm.LEAF_VALU) == 1
+    assert bmm.bmm_leaf_tiles(bmm.LEAF_VALU) == 2
     assert bmm.bmm_leaf_tiles(bmm.LEAF_MFMA_I8) == 8
     assert bmm.bmm_leaf_tiles(bmm.LEAF_MFMA_F4) == 8
     assert bmm.bmm_leaf_tile_shape(bmm.LEAF_MFMA_I8, 5) == (256, 256)
@@ -149,6 +149,7 @@ def test_leaf_tiles_and_status_strings():
     assert bmm.bmm_leaf_tile_shape(bmm.LEAF_MFMA_I8, 6) == (128, 64)  # 3-deep pipeline
     assert bmm.bmm_leaf_tile_shape(bmm.LEAF_MFMA_I8, 8) == (256, 128)  # LDS-shared 2 x 2 waves
     assert bmm.bmm_leaf_tile_shape(bmm.LEAF_VALU, 1) == (128, 128)
+    assert bmm.bmm_leaf_tile_shape(bmm.LEAF_VALU, 2) == (512, 1024)  # outer-product form
     assert "gfx950" in bmm.bmm_version()
 
 

@@ -15,7 +15,8 @@ LEAVES = [("valu", 1, 1), ("mfma128x64", 2, 1), ("mfma64x64", 2, 2), ("mfma64x12
           ("mfma_chunk64x128", 2, 7), ("mfma_lds4_256x128", 2, 8),
           ("f4_128x64", 3, 1), ("f4_64x64", 3, 2), ("f4_64x128", 3, 3), ("f4_64x32", 3, 4),
           ("f4_lds256", 3, 5), ("f4_deep128x64", 3, 6), ("f4_chunk64x128", 3, 7),
-          ("f4_lds4_256x128", 3, 8)]
+          ("f4_lds4_256x128", 3, 8),
+          ("valu_outer", 1, 2)]  # VALU outer-product form: B row-major
 
 
 @pytest.fixture(scope="module")
@@ -113,7 +114,7 @@ KPANEL = [(64, 300, 130, 64), (100, 1000, 70, 128), (130, 4096, 200, 2048),
 
 @pytest.mark.parametrize("sname,sr", SEMIRINGS)
 @pytest.mark.parametrize("lname,leaf,tile", [LEAVES[0], LEAVES[1], LEAVES[7], LEAVES[9],
-                                             LEAVES[8], LEAVES[6]])
+                                             LEAVES[8], LEAVES[6], LEAVES[17]])
 def test_k_panels(bmm, sname, sr, lname, leaf, tile):
     """C as the sum of panel products over k (each panel's product XORed / ORed into C
     after the first), fresh and accumulated, against the oracle's plain product."""
@@ -128,6 +129,25 @@ def test_k_panels(bmm, sname, sr, lname, leaf, tile):
         C0 = gen(m, n, 31 + i, 0xC0)
         got = run(bmm, sr, leaf, tile, A, B, m, k, n, acc_init=C0, k_panel=kp)
         assert np.array_equal(got, (want ^ C0) if sr == oracle.GF2 else (want | C0)), kp
+
+
+@pytest.mark.parametrize("sname,sr", SEMIRINGS)
+def test_valu_outer_wide_shapes(bmm, sname, sr):
+    """The VALU leaf's outer-product form on shapes that span whole 1024-column tiles and a
+    ragged last one, several 512-row tiles and ragged k; B given row-major (read where it
+    lies) and transposed (transposed back into scratch), fresh and accumulated."""
+    for i, (m, k, n) in enumerate([(600, 777, 1100), (513, 2048, 2048), (64, 64, 1024),
+                                   (1030, 100, 2100), (40, 3000, 1088)]):
+        p = None if sr == oracle.GF2 else bmmgen.Dist.inv_sqrt(k)
+        A = gen(m, k, 51 + i, bmmgen.TAG_A, p)
+        B = gen(k, n, 51 + i, bmmgen.TAG_B, p)
+        want = oracle.mul(A, B, k, n, sr)
+        announce("valu outer", sname, (m, k, n))
+        assert np.array_equal(run(bmm, sr, 1, 2, A, B, m, k, n, pad=i % 2), want), (m, k, n)
+        assert np.array_equal(run(bmm, sr, 1, 2, A, B, m, k, n, b_t=True), want), (m, k, n)
+        C0 = gen(m, n, 51 + i, 0xC0)
+        got = run(bmm, sr, 1, 2, A, B, m, k, n, acc_init=C0, pad=1)
+        assert np.array_equal(got, (want ^ C0) if sr == oracle.GF2 else (want | C0)), (m, k, n)
 
 
 def test_k_zero_and_empty(bmm):
@@ -145,7 +165,7 @@ def test_padding_bits_written_zero(bmm):
     m, k, n = 70, 100, 33
     A = gen(m, k, 9, bmmgen.TAG_A)
     B = gen(k, n, 9, bmmgen.TAG_B)
-    for leaf, tile in [(1, 1), (2, 1), (2, 4)]:
+    for leaf, tile in [(1, 1), (1, 2), (2, 1), (2, 4)]:
         announce("padding", leaf, tile)
         got = run(bmm, oracle.BOOLEAN, leaf, tile, A, B, m, k, n)
         assert not (got[:, 0] >> np.uint64(33)).any()
