@@ -343,10 +343,12 @@ __device__ __forceinline__ void tile(const uint64_t* __restrict__ A, int64_t lda
       __builtin_amdgcn_sched_barrier(0);
       // a wave issuing its matrix-core block takes issue priority over the other wave
       // of its SIMD (which is then typically in its first loads or its epilogue); the
-      // short tiles of the recursion gain from it, the long-k loop does not
-      __builtin_amdgcn_s_setprio(1);
+      // short tiles of the recursion gain from it, the long-k loop does not.  int8 only:
+      // the E2M1 build of this pipeline (which spills) returned wrong words with two
+      // waves per SIMD while it raised its priority, and exact ones without the raise.
+      if constexpr (FMT == FMT_I8) __builtin_amdgcn_s_setprio(1);
       compute(xa[s % NB], xb[s % NB]);
-      __builtin_amdgcn_s_setprio(0);
+      if constexpr (FMT == FMT_I8) __builtin_amdgcn_s_setprio(0);
     }
     epilogue<SEMI, RA, RB, FMT>(acc, Cm, ldc, m, n, tm, tn, accumulate, semiring);
     return;

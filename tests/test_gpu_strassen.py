@@ -255,9 +255,11 @@ def test_strassen_shifted_leaf_accumulate_inplace(bmm, scheme, alt):
 
 @pytest.mark.parametrize("leaf", [2, 3])
 @pytest.mark.parametrize("m,k,n,depth", [(8192, 8192, 8192, 2), (8192, 8192, 4096, 1),
-                                         (8192, 4096, 2048, 1)])
+                                         (8192, 4096, 2048, 1), (4096, 4096, 4096, 1)])
 def test_strassen_deep_pipeline_leaf(bmm, leaf, m, k, n, depth):
-    """Tile 6: leaves with k = 2048 or 4096 bits run the fully unrolled 3-deep pipeline."""
+    """Tile 6: int8 leaves with k = 2048 or 4096 bits run the fully unrolled 3-deep
+    pipeline, fp4 leaves the 2-step loop; batched 2048^3 and 4096^3 leaves (7 and 49 per
+    launch) with two waves per SIMD."""
     import torch
     seed = 901 + m + depth + leaf
     A = bmmgen.fill_cpu(m, k, seed, bmmgen.TAG_A, bmmgen.Dist.half())
