@@ -325,8 +325,8 @@ int bmm_compress(int levels, int scheme, const uint64_t* src, uint64_t* dst, int
  * 1..count; 0 = auto), and the C tile (rows x columns) of a variant (per workgroup for
  * the VALU leaf, per wave for the matrix-core leaves).  The VALU leaf's tile 1 is the
  * dot-product form against B^T (128 x 128); tile 2 is the outer-product form (512 x
- * 1024): each bit of A selects a row of B, whose words the wave holds in scalar
- * registers, and the accumulators are the result bits.  Tile 2 reads B row-major, so it
+ * 1024): each bit of A selects a row of B, whose words the waves read from LDS at one
+ * address per wave, and the accumulators are the result bits.  Tile 2 reads B row-major, so it
  * serves the cubic products only (a B passed transposed is transposed back into
  * scratch first); batched leaves (the recursion, bmm_batched) given VALU tile 2 run
  * tile 1. */

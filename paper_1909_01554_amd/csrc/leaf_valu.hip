@@ -151,115 +151,144 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void l
 
 // Outer-product form (tile 2), for cubic products whose B is at hand row-major: every
 // bit A[i][j] selects row j of B, C[i][.] ^= (A[i][j] ? B[j][.] : 0) (GF(2)) or |=
-// (Boolean), 32 columns per v_bitop3_b32 with the selection as a sign-extended mask.  A
-// wave owns 256 rows (four per lane) and 512 columns (16 dwords) of C; the words of row j
-// of B that the wave needs are the same for all its lanes, so they are read with scalar
-// loads into scalar registers and each fold reads one vector register besides its
-// accumulator (no LDS).  The accumulators are the result bits themselves: no reduction.
-// The four waves of a workgroup own 1024 rows over the same columns, so they read the
-// same rows of B (scalar cache hits).  Scalar loads may complete out of order, so a use
-// waits for every one in flight: row j + 1 is requested right after row j's first use,
-// and its latency hides behind the rest of row j's folds and the other waves of the SIMD.
+// (Boolean), 32 columns per v_bitop3_b32 with the bit as a sign-extended mask
+// (v_bfe_i32).  The accumulators are the result bits themselves: no reduction.
+//
+// A wave owns 256 rows (four per lane) and 512 columns (16 dwords); a workgroup 2 x 2
+// waves, 512 x 1024.  Row j's 16 words are the same for all lanes of a wave: they are read
+// from LDS at one address for the whole wave (a broadcast) one step ahead, and each word
+// feeds four folds, one per row of the lane: a lane receives one byte per fold, as in the
+// dot-product form, but the wave's lanes all read the same address.  Stages of OST rows of B (the
+// workgroup's 1024 columns, 8 KB) are double buffered in LDS and loaded one stage ahead
+// into registers; the k-dwords of A are loaded a k-dword ahead.  128 registers leave four
+// waves per SIMD, which the VALU needs to pair instructions: with eight rows per lane (two
+// waves per SIMD) it issued 1.14 instead of 1.39 instructions per SIMD quad-cycle.
 constexpr int OROWS = 4;             // rows per lane
 constexpr int OCW = 16;              // C dwords (32 columns each) per wave
-constexpr int OTM = 4 * 64 * OROWS;  // rows per workgroup
-constexpr int OTN = 32 * OCW;        // columns per workgroup
+constexpr int OST = 64;              // rows of B per LDS stage
+constexpr int OWG_CW = 2 * OCW;      // C dwords per workgroup row (two waves across)
+constexpr int OTM = 2 * 64 * OROWS;  // rows per workgroup
+constexpr int OTN = 32 * OWG_CW;     // columns per workgroup
 
-template <bool FULL>
-__device__ __forceinline__ void outer_row(const uint32_t* __restrict__ r, int ncw,
-                                          uint32_t (&bw)[OCW]) {
-#pragma unroll
-  for (int c = 0; c < OCW; ++c) bw[c] = (FULL || c < ncw) ? r[c] : 0u;
-}
-
-// The steps of one k-dword a of A (min(left, 32) bits; left > 0): cur holds row j of B on
-// entry and row j + 32 (or nothing past k) on exit; brow points at row j and advances.
-template <int SEMI, bool FULL>
-__device__ __forceinline__ void outer_dword(const uint32_t*& brow, int64_t ldb32, int64_t left,
-                                            int ncw, const uint32_t (&a)[OROWS],
-                                            uint32_t (&cur)[OCW], uint32_t (&acc)[OROWS][OCW]) {
-  const int nsteps = (int)(left < 32 ? left : 32);
-  for (int jb = 0; jb < nsteps; ++jb) {
-    uint32_t msk[OROWS];
-#pragma unroll
-    for (int r = 0; r < OROWS; ++r) msk[r] = (uint32_t)__builtin_amdgcn_sbfe((int)a[r], jb, 1);
-#pragma unroll
-    for (int r = 0; r < OROWS; ++r) acc[r][0] = fold<SEMI>(msk[r], cur[0], acc[r][0]);
-    __builtin_amdgcn_sched_barrier(0);
-    brow += ldb32;
-    uint32_t nxt[OCW];
-    if (jb + 1 < left) outer_row<FULL>(brow, ncw, nxt);
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int q = 1; q < OCW; ++q)
-#pragma unroll
-      for (int r = 0; r < OROWS; ++r) acc[r][q] = fold<SEMI>(msk[r], cur[q], acc[r][q]);
-#pragma unroll
-    for (int q = 0; q < OCW; ++q) cur[q] = nxt[q];
-  }
-}
-
-// FULL: the rows of B and C hold at least OCW dwords, so every wave reads a whole window
-// of OCW dwords of row j (the last column tile's window is moved left to end at the row's
-// end, and that wave stores only the columns of its own tile); otherwise (n < 512) the
-// loads past the row read zero.
-template <int SEMI, bool FULL>
-__global__ __launch_bounds__(256) void leaf_valu_outer_kernel(
-    const uint64_t* __restrict__ A, int64_t lda, const uint32_t* __restrict__ B, int64_t ldb32,
-    uint64_t* __restrict__ C, int64_t ldc, int64_t m, int64_t k, int64_t n, int64_t tiles_m,
-    int64_t tiles_n, int accumulate) {
-  const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+template <int SEMI>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void
+leaf_valu_outer_kernel(const uint64_t* __restrict__ A, int64_t lda,
+                       const uint32_t* __restrict__ B, int64_t ldb32, uint64_t* __restrict__ C,
+                       int64_t ldc, int64_t m, int64_t k, int64_t n, int64_t tiles_m,
+                       int64_t tiles_n, int accumulate) {
+  // two spare rows per stage: the reads of the next two rows run ahead unconditionally
+  __shared__ __attribute__((aligned(16))) uint32_t sB[2][(OST + 2) * OWG_CW];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wy = wave >> 1, wx = wave & 1;
   const TileCoord c = xcd_tile(blockIdx.x, gridDim.x, tiles_m, tiles_n);
-  const int64_t row0 = c.tm * OTM + wave * (64 * OROWS);
-  const int64_t n32 = ((n + 63) >> 6) * 2;  // dwords per row of B and C (whole words)
-  const int64_t own32 = c.tn * OCW;         // first C dword of the wave's own columns
-  // first dword of the window the wave computes
-  const int64_t col32 = FULL ? (own32 + OCW <= n32 ? own32 : n32 - OCW) : own32;
-  const int ncw = (int)(n32 - col32 < OCW ? n32 - col32 : OCW);
-  int64_t ri[OROWS];
-  const uint32_t* arow[OROWS];
+  const int64_t n32 = ((n + 63) >> 6) * 2;      // dwords per row of B and C (whole words)
+  const int64_t wg32 = c.tn * OWG_CW;           // first C dword of the workgroup's columns
+  const int64_t col32 = wg32 + wx * OCW;        // first C dword of the wave's columns
+  const int64_t row0 = c.tm * OTM + wy * (64 * OROWS);
+  // the lane's rows are row0 + lane + 64 r: one pointer and a uniform stride; rows past m
+  // load nothing (their bits stay zero)
+  const int64_t lda32 = 2 * lda, astride = 64 * lda32;
+  const uint32_t* arow0 = reinterpret_cast<const uint32_t*>(A) + (row0 + lane) * lda32;
+  int nrows = 0;  // how many of the lane's rows lie in A
 #pragma unroll
-  for (int r = 0; r < OROWS; ++r) {
-    ri[r] = row0 + 64 * r + lane;
-    const int64_t g = ri[r] < m ? ri[r] : m - 1;
-    arow[r] = reinterpret_cast<const uint32_t*>(A + g * lda);
-  }
+  for (int r = 0; r < OROWS; ++r) nrows += row0 + 64 * r + lane < m;
+  auto load_a = [&](int64_t jw, uint32_t (&dst)[OROWS]) {
+#pragma unroll
+    for (int r = 0; r < OROWS; ++r) dst[r] = r < nrows ? arow0[r * astride + jw] : 0u;
+  };
+  // stage loads: OST rows x 32 dwords = 2048 dwords per stage, 8 per thread: thread t
+  // carries row t / 4, dwords 8 (t mod 4) .. + 7
+  const int srow = tid >> 2, sd = (tid & 3) * 8;
+  const int64_t sc = wg32 + sd;  // first B dword this thread stages
+  auto stage_load = [&](int64_t j0, uint4 (&v)[2]) {
+    const int64_t j = j0 + srow;
+    if (j < k && sc + 8 <= n32) {
+      const uint4* src = reinterpret_cast<const uint4*>(B + j * ldb32 + sc);
+      v[0] = src[0];
+      v[1] = src[1];
+    } else {
+      uint32_t t[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) t[q] = (j < k && sc + q < n32) ? B[j * ldb32 + sc + q] : 0u;
+      v[0] = make_uint4(t[0], t[1], t[2], t[3]);
+      v[1] = make_uint4(t[4], t[5], t[6], t[7]);
+    }
+  };
+  auto stage_store = [&](int buf, const uint4 (&v)[2]) {
+    uint4* dst = reinterpret_cast<uint4*>(&sB[buf][srow * OWG_CW + sd]);
+    dst[0] = v[0];
+    dst[1] = v[1];
+  };
   uint32_t acc[OROWS][OCW];
 #pragma unroll
   for (int r = 0; r < OROWS; ++r)
 #pragma unroll
     for (int q = 0; q < OCW; ++q) acc[r][q] = 0u;
-  // One step per bit j of k (outer_dword), 32 per k-dword of A. The k-dwords of A
-  // alternate between two register sets, each loaded a whole k-dword ahead of its use
-  // (the last one is reread rather than skipped, so no copy waits for a load).
-  const int64_t k32 = (k + 31) >> 5;  // k-dwords of A
-  const uint32_t* brow = B + col32;
-  uint32_t a0[OROWS], a1[OROWS], cur[OCW];
+  const int64_t k32 = (k + 31) >> 5;
+  uint32_t a[OROWS], an[OROWS];
 #pragma unroll
-  for (int r = 0; r < OROWS; ++r) a0[r] = arow[r][0];
-  outer_row<FULL>(brow, ncw, cur);
-  for (int64_t jw = 0; jw < k32; jw += 2) {
-    const int64_t j1 = jw + 1 < k32 ? jw + 1 : k32 - 1;
+  for (int r = 0; r < OROWS; ++r) an[r] = 0u;
+  if (k > 0) load_a(0, an);
+  uint4 sv[2];
+  stage_load(0, sv);
+  stage_store(0, sv);
+  const int64_t stages = (k + OST - 1) / OST;
+  if (stages > 1) stage_load(OST, sv);
+  __syncthreads();
+  // one step: the row masks of bit j of A, and the folds of row j of B (bw, 16 words)
+  auto step = [&](int jb, const uint4 (&bv)[4]) {
+    uint32_t msk[OROWS];
 #pragma unroll
-    for (int r = 0; r < OROWS; ++r) a1[r] = arow[r][j1];
-    outer_dword<SEMI, FULL>(brow, ldb32, k - 32 * jw, ncw, a0, cur, acc);
-    if (jw + 1 >= k32) break;
-    const int64_t j2 = jw + 2 < k32 ? jw + 2 : k32 - 1;
+    for (int r = 0; r < OROWS; ++r) msk[r] = (uint32_t)__builtin_amdgcn_sbfe((int)a[r], jb, 1);
+    const uint32_t bw[OCW] = {bv[0].x, bv[0].y, bv[0].z, bv[0].w, bv[1].x, bv[1].y,
+                              bv[1].z, bv[1].w, bv[2].x, bv[2].y, bv[2].z, bv[2].w,
+                              bv[3].x, bv[3].y, bv[3].z, bv[3].w};
 #pragma unroll
-    for (int r = 0; r < OROWS; ++r) a0[r] = arow[r][j2];
-    outer_dword<SEMI, FULL>(brow, ldb32, k - 32 * (jw + 1), ncw, a1, cur, acc);
+    for (int q = 0; q < OCW; ++q)
+#pragma unroll
+      for (int r = 0; r < OROWS; ++r) acc[r][q] = fold<SEMI>(msk[r], bw[q], acc[r][q]);
+  };
+  auto read_row = [&](const uint32_t* rowp, uint4 (&bv)[4]) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) bv[q] = reinterpret_cast<const uint4*>(rowp)[q];
+  };
+  for (int64_t st = 0; st < stages; ++st) {
+    const int cur = (int)(st & 1);
+    const uint32_t* base = &sB[cur][wx * OCW];
+    const int64_t j0 = st * OST;
+    const int nsteps = (int)(k - j0 < OST ? k - j0 : OST);
+    // two steps per iteration with two row buffers (no copies); rows j + 1 and j + 2 are
+    // requested before row j's and row j + 1's folds (the spare rows absorb the overrun)
+    uint4 b0[4], b1[4];
+    read_row(base, b0);
+    for (int jj = 0; jj < nsteps; jj += 2) {
+      const int64_t j = j0 + jj;
+      if ((j & 31) == 0) {  // uniform: this k-dword of A, and the next one requested
+#pragma unroll
+        for (int r = 0; r < OROWS; ++r) a[r] = an[r];
+        load_a((j >> 5) + 1 < k32 ? (j >> 5) + 1 : k32 - 1, an);
+      }
+      read_row(base + (jj + 1) * OWG_CW, b1);
+      step((int)(j & 31), b0);
+      read_row(base + (jj + 2) * OWG_CW, b0);
+      step((int)((j + 1) & 31), b1);  // row nsteps of a ragged last stage is zero
+    }
+    if (st + 1 < stages) {
+      stage_store(cur ^ 1, sv);
+      if (st + 2 < stages) stage_load((st + 2) * OST, sv);
+    }
+    __syncthreads();
   }
   // the accumulators are C's dwords: two make a 64-bit word of the row
-  const int64_t nw = n32 >> 1, w0 = col32 >> 1, own = own32 >> 1;
+  const int64_t nw = n32 >> 1, w0 = col32 >> 1;
 #pragma unroll
   for (int r = 0; r < OROWS; ++r) {
-    if (ri[r] >= m) continue;
-    uint64_t* dst = C + ri[r] * ldc + w0;
+    if (r >= nrows) continue;
+    uint64_t* dst = C + (row0 + 64 * r + lane) * ldc + w0;
 #pragma unroll
     for (int w = 0; w < OCW / 2; ++w) {
       if (w0 + w >= nw) break;  // uniform
-      if (w0 + w < own) continue;  // uniform: the previous tile's columns
       uint64_t x = (uint64_t)acc[r][2 * w] | ((uint64_t)acc[r][2 * w + 1] << 32);
       const int64_t c0 = (w0 + w) * 64;
       if (n - c0 < 64) x &= (1ull << (n - c0)) - 1ull;  // padding columns stay zero
@@ -296,23 +325,13 @@ hipError_t launch_leaf_valu_outer(int semiring, const uint64_t* A, int64_t lda,
   const int64_t blocks = tiles_m * tiles_n;
   if (!grid_fits(blocks, 256)) return kGridTooLarge;
   const uint32_t* B32 = reinterpret_cast<const uint32_t*>(B);
-  const bool full = ((n + 63) / 64) * 2 >= OCW;
   const dim3 g((unsigned)blocks), b(256);
-  if (semiring == GF2) {
-    if (full)
-      hipLaunchKernelGGL((leaf_valu_outer_kernel<GF2, true>), g, b, 0, s, A, lda, B32, 2 * ldb,
-                         C, ldc, m, k, n, tiles_m, tiles_n, accumulate);
-    else
-      hipLaunchKernelGGL((leaf_valu_outer_kernel<GF2, false>), g, b, 0, s, A, lda, B32, 2 * ldb,
-                         C, ldc, m, k, n, tiles_m, tiles_n, accumulate);
-  } else {
-    if (full)
-      hipLaunchKernelGGL((leaf_valu_outer_kernel<BOOLEAN, true>), g, b, 0, s, A, lda, B32,
-                         2 * ldb, C, ldc, m, k, n, tiles_m, tiles_n, accumulate);
-    else
-      hipLaunchKernelGGL((leaf_valu_outer_kernel<BOOLEAN, false>), g, b, 0, s, A, lda, B32,
-                         2 * ldb, C, ldc, m, k, n, tiles_m, tiles_n, accumulate);
-  }
+  if (semiring == GF2)
+    hipLaunchKernelGGL(leaf_valu_outer_kernel<GF2>, g, b, 0, s, A, lda, B32, 2 * ldb, C, ldc,
+                       m, k, n, tiles_m, tiles_n, accumulate);
+  else
+    hipLaunchKernelGGL(leaf_valu_outer_kernel<BOOLEAN>, g, b, 0, s, A, lda, B32, 2 * ldb, C,
+                       ldc, m, k, n, tiles_m, tiles_n, accumulate);
   return hipGetLastError();
 }
 

@@ -133,11 +133,13 @@ def test_k_panels(bmm, sname, sr, lname, leaf, tile):
 
 @pytest.mark.parametrize("sname,sr", SEMIRINGS)
 def test_valu_outer_wide_shapes(bmm, sname, sr):
-    """The VALU leaf's outer-product form on shapes that span whole 1024-column tiles and a
-    ragged last one, several 512-row tiles and ragged k; B given row-major (read where it
-    lies) and transposed (transposed back into scratch), fresh and accumulated."""
-    for i, (m, k, n) in enumerate([(600, 777, 1100), (513, 2048, 2048), (64, 64, 1024),
-                                   (1030, 100, 2100), (40, 3000, 1088)]):
+    """The VALU leaf's outer-product form on shapes that span whole 512 x 1024 tiles and
+    ragged last ones, and k within one 64-row stage of B, over several, odd, and ending one
+    row into a stage; B given row-major (read where it lies) and transposed (transposed
+    back into scratch), fresh and accumulated."""
+    for i, (m, k, n) in enumerate([(600, 777, 1100), (1025, 2048, 2048), (64, 64, 1024),
+                                   (2100, 100, 2100), (40, 3000, 1088), (300, 1, 70),
+                                   (130, 129, 3000), (2048, 63, 64)]):
         p = None if sr == oracle.GF2 else bmmgen.Dist.inv_sqrt(k)
         A = gen(m, k, 51 + i, bmmgen.TAG_A, p)
         B = gen(k, n, 51 + i, bmmgen.TAG_B, p)
