@@ -397,7 +397,7 @@ def run_cubic(args, torch, np, bmm, bmmgen):
                 "frac_of_peak": round(bops / t / 1e12 / peaks[leaf], 4),
                 "verified_rows": len(rows), "verified": bool(np.array_equal(got, want))}
             log(f"[bench] cubic {sname} {names[leaf]}: {out[f'{sname}_{names[leaf]}']}")
-        del A, BT, C
+        del A, BT, Bop, C
         torch.cuda.empty_cache()
     print(json.dumps(out), flush=True)
 
@@ -435,12 +435,14 @@ def run_valu(args, torch, np, bmm, bmmgen):
     """The VALU roofline: the issue-rate calibration kernel, then the VALU leaf on
     the cubic products at one size (GF(2) on Bernoulli(1/2) bits, Boolean on
     Bernoulli(n^-1/2) bits), each as a fraction of the single-issue and the
-    dual-issue bit-operation peaks; 64 stratified rows of each checked."""
+    dual-issue bit-operation peaks; 64 stratified rows of each checked.  --tile 2
+    runs the leaf's outer-product form (B row-major) instead of the dot-product form."""
     import oracle
     n = args.n
+    outer = args.tile == 2
     cal = valu_calibration(bmm)
     sustained = sustained_valu_tbops(cal)
-    out = {"mode": "valu", "n": n, "calibration": cal,
+    out = {"mode": "valu", "n": n, "tile": 2 if outer else 1, "calibration": cal,
            "peaks_tbops": {"single_issue_64_lanes": PEAK_VALU_SINGLE_TBOPS,
                            "dual_issue_128_lanes": PEAK_VALU_FUSED_TBOPS,
                            "sustained_measured": round(sustained, 1)}}
@@ -453,21 +455,25 @@ def run_valu(args, torch, np, bmm, bmmgen):
                              bmmgen.Dist.pow2(max(1, (n.bit_length() - 1) // 2)))]:
         A = torch.empty((n, n // 64), dtype=torch.int64, device=dev)
         B = torch.empty_like(A)
-        BT = torch.empty_like(A)
+        BT = None if outer else torch.empty_like(A)
         C = torch.empty_like(A)
         bmmgen.fill_tensor(A, n, n, seed, 0xA if sr == bmm.GF2 else 0x1A, dist)
         bmmgen.fill_tensor(B, n, n, seed, 0xB if sr == bmm.GF2 else 0x1B, dist)
-        bmm.bmm_transpose(B, BT, n, n)
+        if outer:
+            Bop = B  # the outer-product form reads B where it lies
+        else:
+            bmm.bmm_transpose(B, BT, n, n)
+            Bop = BT
         del B
         fn = bmm.bmm_gf2 if sr == bmm.GF2 else bmm.bmm_boolean
-        o = bmm.Options(leaf=bmm.LEAF_VALU)
+        o = bmm.Options(leaf=bmm.LEAF_VALU, tile=2 if outer else 1)
         for _ in range(args.warmup):
-            fn(A, BT, C, n, n, n, options=o, b_transposed=True)
+            fn(A, Bop, C, n, n, n, options=o, b_transposed=not outer)
         times = []
         for _ in range(args.steps):
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record()
-            fn(A, BT, C, n, n, n, options=o, b_transposed=True)
+            fn(A, Bop, C, n, n, n, options=o, b_transposed=not outer)
             e1.record()
             torch.cuda.synchronize()
             times.append(e0.elapsed_time(e1) / 1e3)
