@@ -397,7 +397,7 @@ def run_cubic(args, torch, np, bmm, bmmgen):
                 "frac_of_peak": round(bops / t / 1e12 / peaks[leaf], 4),
                 "verified_rows": len(rows), "verified": bool(np.array_equal(got, want))}
             log(f"[bench] cubic {sname} {names[leaf]}: {out[f'{sname}_{names[leaf]}']}")
-        del A, BT, Bop, C
+        del A, BT, C
         torch.cuda.empty_cache()
     print(json.dumps(out), flush=True)
 
@@ -488,7 +488,7 @@ def run_valu(args, torch, np, bmm, bmmgen):
                       **valu_fracs(rate, sustained),
                       "verified_rows": len(rows), "verified": bool(np.array_equal(got, want))}
         log(f"[bench] VALU leaf {sname}: {out[sname]}")
-        del A, BT, C
+        del A, BT, Bop, C
         torch.cuda.empty_cache()
     print(json.dumps(out), flush=True)
 
