@@ -116,12 +116,13 @@ hipError_t launch_t(const LeafBatch& p, hipStream_t s) {
       return hipGetLastError();
     }
   }
+  constexpr bool kWideForm = FMT == mfma::FMT_I8;  // the fp4 wide form spills these tiles
   if (aligned16)
-    hipLaunchKernelGGL((leaf_mfma_kernel<SEMI, RA, RB, 2, FMT>), dim3((unsigned)blocks), dim3(256), 0, s,
-                       p, tiles_m, tiles_n);
+    hipLaunchKernelGGL((leaf_mfma_kernel<SEMI, RA, RB, 2, FMT, 2, 0, kWideForm>), dim3((unsigned)blocks),
+                       dim3(256), 0, s, p, tiles_m, tiles_n);
   else
-    hipLaunchKernelGGL((leaf_mfma_kernel<SEMI, RA, RB, 1, FMT>), dim3((unsigned)blocks), dim3(256), 0, s,
-                       p, tiles_m, tiles_n);
+    hipLaunchKernelGGL((leaf_mfma_kernel<SEMI, RA, RB, 1, FMT, 2, 0, kWideForm>), dim3((unsigned)blocks),
+                       dim3(256), 0, s, p, tiles_m, tiles_n);
   return hipGetLastError();
 }
 

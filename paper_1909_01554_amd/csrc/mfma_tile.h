@@ -66,11 +66,45 @@ __device__ __forceinline__ v4i expand4(uint32_t x, int first) {
   return o;
 }
 
-// WIDE: expand the rows of the tile's longer side with 64-bit shifts (below).
+// WIDE: expand the rows of the tile's longer side with 64-bit shifts (below).  For E2M1
+// operands the wide form holds twice the expanded rows: the LDS-staged 256 x 256 leaf
+// takes it (2-3% faster); the register-fed fp4 tiles and the batched items, whose
+// registers it would spill, keep the 32-bit form.
 template <int SEMI, int RA, int RB, int FMT, bool WIDE = true>
 __device__ __forceinline__ void mfma_word(const uint64_t (&xa)[RA], const uint64_t (&xb)[RB],
                                           typename Acc<FMT>::type (&acc)[RA][RB]) {
-  if constexpr (FMT == FMT_F4) {
+  if constexpr (FMT == FMT_F4 && WIDE) {
+    // one MFMA per 32-bit half: 32 k values per lane, 64 per instruction; the rows of
+    // the longer side expand both halves at once (a 64-bit shift and two masks give
+    // dword d of each half, where the 32-bit form takes two shifts and two masks)
+    constexpr bool BW = RB >= RA;
+    constexpr int NW = BW ? RB : RA, NN = BW ? RA : RB;
+    v8i ow[2][NW];
+#pragma unroll
+    for (int g = 0; g < NW; ++g) {
+#pragma unroll
+      for (int d = 0; d < 4; ++d) {
+        const uint64_t y = ((BW ? xb[g] : xa[g]) >> d) & 0x1111111111111111ull;
+        ow[0][g][d] = (int)(uint32_t)y;
+        ow[1][g][d] = (int)(uint32_t)(y >> 32);
+      }
+#pragma unroll
+      for (int d = 4; d < 8; ++d) ow[0][g][d] = ow[1][g][d] = 0;
+    }
+#pragma unroll
+    for (int hw = 0; hw < 2; ++hw) {
+      v8i on[NN];
+#pragma unroll
+      for (int f = 0; f < NN; ++f) on[f] = expand_f4((uint32_t)((BW ? xa[f] : xb[f]) >> (32 * hw)));
+#pragma unroll
+      for (int f = 0; f < RA; ++f)
+#pragma unroll
+        for (int g = 0; g < RB; ++g)
+          acc[f][g] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+              BW ? on[f] : ow[hw][f], BW ? ow[hw][g] : on[g], acc[f][g], 4, 4, 0, 127, 0, 127);
+    }
+    return;
+  } else if constexpr (FMT == FMT_F4) {
     // one MFMA per 32-bit half: 32 k values per lane, 64 per instruction
 #pragma unroll
     for (int hw = 0; hw < 2; ++hw) {
