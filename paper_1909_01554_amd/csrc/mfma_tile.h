@@ -68,16 +68,17 @@ __device__ __forceinline__ v4i expand4(uint32_t x, int first) {
 
 // WIDE: expand the rows of the tile's longer side with 64-bit shifts (below).  For E2M1
 // operands the wide form holds twice the expanded rows: the LDS-staged 256 x 256 leaf
-// takes it (2-3% faster); the register-fed fp4 tiles and the batched items, whose
-// registers it would spill, keep the 32-bit form.
-template <int SEMI, int RA, int RB, int FMT, bool WIDE = true>
+// takes it (2-3% faster); the register-fed fp4 tiles keep the 32-bit form, which it would
+// spill, and the batched items widen only their shorter side (F4SHORT; the longer one
+// spills them).
+template <int SEMI, int RA, int RB, int FMT, bool WIDE = true, bool F4SHORT = false>
 __device__ __forceinline__ void mfma_word(const uint64_t (&xa)[RA], const uint64_t (&xb)[RB],
                                           typename Acc<FMT>::type (&acc)[RA][RB]) {
   if constexpr (FMT == FMT_F4 && WIDE) {
     // one MFMA per 32-bit half: 32 k values per lane, 64 per instruction; the rows of
     // the longer side expand both halves at once (a 64-bit shift and two masks give
     // dword d of each half, where the 32-bit form takes two shifts and two masks)
-    constexpr bool BW = RB >= RA;
+    constexpr bool BW = F4SHORT ? RB < RA : RB >= RA;
     constexpr int NW = BW ? RB : RA, NN = BW ? RA : RB;
     v8i ow[2][NW];
 #pragma unroll
@@ -541,7 +542,8 @@ struct LdsNoNext {
 // caller's wave 0 names the next item there); after that barrier, before the epilogue,
 // prefetch(stage) may load the next item's first stage into `stage` and returns whether
 // it did, which lds_item returns.
-template <int SEMI, int FMT, bool WIDE, class AtLast = LdsNoNext, class Prefetch = LdsNoNext>
+template <int SEMI, int FMT, bool WIDE, bool F4SHORT = false, class AtLast = LdsNoNext,
+          class Prefetch = LdsNoNext>
 __device__ __forceinline__ bool lds_item(const uint64_t* Ap, int64_t lda, const uint64_t* BTp,
                                          int64_t ldbt, uint64_t* C, int64_t ldc, int64_t m,
                                          int64_t k, int64_t n, int64_t im, int64_t in,
@@ -609,8 +611,8 @@ __device__ __forceinline__ bool lds_item(const uint64_t* Ap, int64_t lda, const 
         xb[0][g] = v.x;
         xb[1][g] = v.y;
       }
-      mfma_word<SEMI, RA, RB, FMT, WIDE>(xa[0], xb[0], acc);
-      mfma_word<SEMI, RA, RB, FMT, WIDE>(xa[1], xb[1], acc);
+      mfma_word<SEMI, RA, RB, FMT, WIDE, F4SHORT>(xa[0], xb[0], acc);
+      mfma_word<SEMI, RA, RB, FMT, WIDE, F4SHORT>(xa[1], xb[1], acc);
     }
     if (st + 1 < stages)
       store(cur ^ 1);
