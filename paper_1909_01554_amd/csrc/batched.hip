@@ -69,9 +69,9 @@ __device__ __forceinline__ void resolve_item(const BatchedSeg* __restrict__ segs
   }
 }
 
-// The 32-bit operand expansion: the persistent loop's own state leaves no room
-// for the wide form's registers.  The LDS-shared fp4 items widen the shorter side
-// only (1.5-2% faster; the longer side spills).
+// The register-fed items keep the 32-bit operand expansion: the persistent loop's own
+// state leaves no room for the wide form's registers.  The LDS-shared items widen their
+// shorter side (its two B^T rows; int8 33.0 -> 32.1 ms, fp4 24.2 -> 23.8 ms).
 constexpr bool kWide = false;
 
 template <int RA, int RB, int FMT>
@@ -127,7 +127,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
     const BatchedDesc& d = descs[p];
     int64_t im, in;
     band_coord(item, d.items_m, d.items_n, im, in);
-    mfma::lds_item<mfma::SEMI_ANY, FMT, kWide || FMT == mfma::FMT_F4, true>(
+    mfma::lds_item<mfma::SEMI_ANY, FMT, true, true>(
         d.A, d.lda, d.BT, d.ldbt, d.C, d.ldc, d.m, d.k, d.n, im, in, d.tiles_m, d.tiles_n,
         d.aligned != 0, 0, d.semiring, w, smem, stage);
     if (w == 0) resolve_item(segs, qs, counters, __shfl(v, 0), q, visited, lane, slots[(it + 1) & 1]);

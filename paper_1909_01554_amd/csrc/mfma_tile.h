@@ -66,19 +66,20 @@ __device__ __forceinline__ v4i expand4(uint32_t x, int first) {
   return o;
 }
 
-// WIDE: expand the rows of the tile's longer side with 64-bit shifts (below).  For E2M1
-// operands the wide form holds twice the expanded rows: the LDS-staged 256 x 256 leaf
-// takes it (2-3% faster); the register-fed fp4 tiles keep the 32-bit form, which it would
-// spill, and the batched items widen only their shorter side (F4SHORT; the longer one
-// spills them).
-template <int SEMI, int RA, int RB, int FMT, bool WIDE = true, bool F4SHORT = false>
+// WIDE: expand the rows of one side of the tile with 64-bit shifts (below): the longer
+// side, or with SHORT the shorter one, which holds fewer expanded rows in registers.  The
+// LDS-staged 256 x 256 leaf widens its longer side (2-3% faster for E2M1 operands); the
+// batched items widen their shorter side (3% faster for int8, 2% for E2M1; the longer
+// side spills them); the register-fed fp4 tiles keep the 32-bit form, which either wide
+// form would spill.
+template <int SEMI, int RA, int RB, int FMT, bool WIDE = true, bool SHORT = false>
 __device__ __forceinline__ void mfma_word(const uint64_t (&xa)[RA], const uint64_t (&xb)[RB],
                                           typename Acc<FMT>::type (&acc)[RA][RB]) {
   if constexpr (FMT == FMT_F4 && WIDE) {
     // one MFMA per 32-bit half: 32 k values per lane, 64 per instruction; the rows of
     // the longer side expand both halves at once (a 64-bit shift and two masks give
     // dword d of each half, where the 32-bit form takes two shifts and two masks)
-    constexpr bool BW = F4SHORT ? RB < RA : RB >= RA;
+    constexpr bool BW = SHORT ? RB < RA : RB >= RA;
     constexpr int NW = BW ? RB : RA, NN = BW ? RA : RB;
     v8i ow[2][NW];
 #pragma unroll
@@ -146,7 +147,7 @@ __device__ __forceinline__ void mfma_word(const uint64_t (&xa)[RA], const uint64
       // 64-bit shift and two masks give dword d of each half, where the 32-bit form takes
       // two shifts and two masks.  Holding both halves for every row would need more
       // registers than two waves per SIMD leave, so the other side stays 32-bit.
-      constexpr bool BW = RB >= RA;
+      constexpr bool BW = SHORT ? RB < RA : RB >= RA;
       v4i ow[2][BW ? RB : RA];
 #pragma unroll
       for (int g = 0; g < (BW ? RB : RA); ++g)
@@ -300,7 +301,8 @@ __device__ __forceinline__ void epilogue(const typename Acc<FMT>::type (&acc)[RA
 // (k = 128 * KV * STEPS bits); the loop then unrolls completely, so the
 // compiler knows every load in flight, and NB register buffers keep the words
 // of step st + NB - 1 in flight while step st computes.
-template <int SEMI, int RA, int RB, int KV, int FMT, int NB = 2, int STEPS = 0, bool WIDE = true>
+template <int SEMI, int RA, int RB, int KV, int FMT, int NB = 2, int STEPS = 0, bool WIDE = true,
+          bool SHORT = false>
 __device__ __forceinline__ void tile(const uint64_t* __restrict__ A, int64_t lda,
                                      const uint64_t* __restrict__ BT, int64_t ldbt,
                                      uint64_t* __restrict__ Cm, int64_t ldc, int64_t m,
@@ -365,7 +367,7 @@ __device__ __forceinline__ void tile(const uint64_t* __restrict__ A, int64_t lda
   };
   auto compute = [&](const uint64_t (&xa)[KV][RA], const uint64_t (&xb)[KV][RB]) {
 #pragma unroll
-    for (int v = 0; v < KV; ++v) mfma_word<SEMI, RA, RB, FMT, WIDE>(xa[v], xb[v], acc);
+    for (int v = 0; v < KV; ++v) mfma_word<SEMI, RA, RB, FMT, WIDE, SHORT>(xa[v], xb[v], acc);
   };
   if constexpr (STEPS > 0) {
     static_assert(STEPS >= NB, "an unrolled pipeline needs at least NB steps");
@@ -456,7 +458,7 @@ tail:
         for (int f = 0; f < RA; ++f) xa[f] = wi < kw ? arow[f][w - adv + v] : 0ull;
 #pragma unroll
         for (int g = 0; g < RB; ++g) xb[g] = wi < kw ? brow[g][w - adv + v] : 0ull;
-        mfma_word<SEMI, RA, RB, FMT, WIDE>(xa, xb, acc);
+        mfma_word<SEMI, RA, RB, FMT, WIDE, SHORT>(xa, xb, acc);
       }
     }
   }
@@ -542,7 +544,7 @@ struct LdsNoNext {
 // caller's wave 0 names the next item there); after that barrier, before the epilogue,
 // prefetch(stage) may load the next item's first stage into `stage` and returns whether
 // it did, which lds_item returns.
-template <int SEMI, int FMT, bool WIDE, bool F4SHORT = false, class AtLast = LdsNoNext,
+template <int SEMI, int FMT, bool WIDE, bool SHORT = false, class AtLast = LdsNoNext,
           class Prefetch = LdsNoNext>
 __device__ __forceinline__ bool lds_item(const uint64_t* Ap, int64_t lda, const uint64_t* BTp,
                                          int64_t ldbt, uint64_t* C, int64_t ldc, int64_t m,
@@ -611,8 +613,8 @@ __device__ __forceinline__ bool lds_item(const uint64_t* Ap, int64_t lda, const 
         xb[0][g] = v.x;
         xb[1][g] = v.y;
       }
-      mfma_word<SEMI, RA, RB, FMT, WIDE, F4SHORT>(xa[0], xb[0], acc);
-      mfma_word<SEMI, RA, RB, FMT, WIDE, F4SHORT>(xa[1], xb[1], acc);
+      mfma_word<SEMI, RA, RB, FMT, WIDE, SHORT>(xa[0], xb[0], acc);
+      mfma_word<SEMI, RA, RB, FMT, WIDE, SHORT>(xa[1], xb[1], acc);
     }
     if (st + 1 < stages)
       store(cur ^ 1);
