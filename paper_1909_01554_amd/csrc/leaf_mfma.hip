@@ -78,10 +78,10 @@ hipError_t launch_lds4(const LeafBatch& p, hipStream_t s) {
 }
 
 // DEEP: int8 leaves of the recursion's lengths (k = 2048 or 4096 bits, 16-byte
-// aligned) run a fully unrolled 3-deep load pipeline.  At k = 2048 the shorter side's
-// rows (two of B^T) expand with 64-bit shifts: 6% fewer VALU instructions, the n = 2^18
-// recursion 2% faster; widening the longer side spilled in the prologue and gained
-// nothing, and k = 4096 keeps the 32-bit expansion.  CHUNKED: aligned int8 leaves
+// aligned) run a fully unrolled 3-deep load pipeline, with the shorter side's rows (two
+// of B^T) expanded by 64-bit shifts: 6% fewer VALU instructions, the n = 2^18 recursion
+// (k = 2048) 2% faster and the n = 65536 one at depth 4 (k = 4096) 2% faster; widening
+// the longer side spilled in the prologue and gained nothing.  CHUNKED: aligned int8 leaves
 // run the 2-deep pipeline as a loop over fully unrolled chunks of 12 steps, which
 // leaves the compiler's conservative wait for outstanding loads at the loop's
 // back edge once per chunk instead of once per step pair.  All else takes the
@@ -107,8 +107,8 @@ hipError_t launch_t(const LeafBatch& p, hipStream_t s) {
       return hipGetLastError();
     }
     if (aligned16 && p.k == 4096) {
-      hipLaunchKernelGGL((leaf_mfma_kernel<SEMI, RA, RB, 2, FMT, 3, 16, false>), g, b, 0, s, p, tiles_m,
-                         tiles_n);
+      hipLaunchKernelGGL((leaf_mfma_kernel<SEMI, RA, RB, 2, FMT, 3, 16, true, true>), g, b, 0, s, p,
+                         tiles_m, tiles_n);
       return hipGetLastError();
     }
   }
