@@ -143,10 +143,11 @@ __device__ __forceinline__ void mfma_word(const uint64_t (&xa)[RA], const uint64
   } else {
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
-      // The rows of the longer side expand both 32-bit halves of a word at once: one
-      // 64-bit shift and two masks give dword d of each half, where the 32-bit form takes
-      // two shifts and two masks.  Holding both halves for every row would need more
-      // registers than two waves per SIMD leave, so the other side stays 32-bit.
+      // The rows of one side (the longer, or with SHORT the shorter) expand both 32-bit
+      // halves of a word at once: one 64-bit shift and two masks give dword d of each
+      // half, where the 32-bit form takes two shifts and two masks.  Holding both halves
+      // for every row would need more registers than two waves per SIMD leave, so the
+      // other side stays 32-bit.
       constexpr bool BW = SHORT ? RB < RA : RB >= RA;
       v4i ow[2][BW ? RB : RA];
 #pragma unroll
