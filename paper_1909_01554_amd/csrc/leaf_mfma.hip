@@ -28,7 +28,7 @@ namespace {
 
 // Each workgroup owns 2 x 2 wave tiles; workgroups are ordered for L2 reuse per XCD.
 template <int SEMI, int RA, int RB, int KV, int FMT, int NB = 2, int STEPS = 0, bool WIDE = true,
-          bool SHORT = false>
+          bool SHORT = false, bool BOTH = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void leaf_mfma_kernel(
     LeafBatch p, int64_t tiles_m, int64_t tiles_n) {
   const int64_t grid_m = (tiles_m + 1) >> 1, grid_n = (tiles_n + 1) >> 1;
@@ -41,7 +41,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void l
   const int64_t tn = 2 * c.tn + (w & 1);
   if (c.b >= p.batch || tm >= tiles_m || tn >= tiles_n) return;  // uniform per wave
   const int64_t b = c.b;
-  mfma::tile<SEMI, RA, RB, KV, FMT, NB, STEPS, WIDE, SHORT>(p.A + b * p.strideA, p.lda, p.BT + b * p.strideB, p.ldbt,
+  mfma::tile<SEMI, RA, RB, KV, FMT, NB, STEPS, WIDE, SHORT, BOTH>(p.A + b * p.strideA, p.lda, p.BT + b * p.strideB, p.ldbt,
                                     p.C + b * p.strideC, p.ldc, p.m, p.k, p.n, tm, tn,
                                     p.accumulate);
 }
@@ -78,10 +78,12 @@ hipError_t launch_lds4(const LeafBatch& p, hipStream_t s) {
 }
 
 // DEEP: int8 leaves of the recursion's lengths (k = 2048 or 4096 bits, 16-byte
-// aligned) run a fully unrolled 3-deep load pipeline, with the shorter side's rows (two
-// of B^T) expanded by 64-bit shifts: 6% fewer VALU instructions, the n = 2^18 recursion
-// (k = 2048) 2% faster and the n = 65536 one at depth 4 (k = 4096) 2% faster; widening
-// the longer side spilled in the prologue and gained nothing.  CHUNKED: aligned int8 leaves
+// aligned) run a fully unrolled load pipeline with 64-bit operand expansion.  k = 4096:
+// 3 register buffers, the shorter side's rows (two of B^T) wide (6% fewer VALU
+// instructions, 2% faster; widening the longer side instead spilled and gained
+// nothing).  k = 2048: 2 buffers and both sides wide (13% fewer VALU instructions than
+// the shorter side alone, the n = 2^18 recursion 1-1.5% faster; with 3 buffers both
+// sides wide spill).  CHUNKED: aligned int8 leaves
 // run the 2-deep pipeline as a loop over fully unrolled chunks of 12 steps, which
 // leaves the compiler's conservative wait for outstanding loads at the loop's
 // back edge once per chunk instead of once per step pair.  All else takes the
@@ -102,8 +104,8 @@ hipError_t launch_t(const LeafBatch& p, hipStream_t s) {
   // spill 1.7-3.9 KB per lane and ran the n = 2^18 fp4 recursion 5.6x slower
   if constexpr (DEEP && FMT == mfma::FMT_I8) {
     if (aligned16 && p.k == 2048) {
-      hipLaunchKernelGGL((leaf_mfma_kernel<SEMI, RA, RB, 2, FMT, 3, 8, true, true>), g, b, 0, s, p,
-                         tiles_m, tiles_n);
+      hipLaunchKernelGGL((leaf_mfma_kernel<SEMI, RA, RB, 2, FMT, 2, 8, true, false, true>), g, b, 0, s,
+                         p, tiles_m, tiles_n);
       return hipGetLastError();
     }
     if (aligned16 && p.k == 4096) {

@@ -71,8 +71,9 @@ __device__ __forceinline__ v4i expand4(uint32_t x, int first) {
 // LDS-staged 256 x 256 leaf widens its longer side (2-3% faster for E2M1 operands); the
 // batched items widen their shorter side (3% faster for int8, 2% for E2M1; the longer
 // side spills them); the register-fed fp4 tiles keep the 32-bit form, which either wide
-// form would spill.
-template <int SEMI, int RA, int RB, int FMT, bool WIDE = true, bool SHORT = false>
+// form would spill.  BOTH (int8): both sides wide, for the recursion's unrolled 128 x 64
+// tile with two load buffers instead of three.
+template <int SEMI, int RA, int RB, int FMT, bool WIDE = true, bool SHORT = false, bool BOTH = false>
 __device__ __forceinline__ void mfma_word(const uint64_t (&xa)[RA], const uint64_t (&xb)[RB],
                                           typename Acc<FMT>::type (&acc)[RA][RB]) {
   if constexpr (FMT == FMT_F4 && WIDE) {
@@ -143,6 +144,35 @@ __device__ __forceinline__ void mfma_word(const uint64_t (&xa)[RA], const uint64
   } else {
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
+      if constexpr (BOTH) {
+        // every row expands both halves at once (16 more registers than one side)
+        v4i owa[2][RA], owb[2][RB];
+#pragma unroll
+        for (int f = 0; f < RA; ++f)
+#pragma unroll
+          for (int d = 0; d < 4; ++d) {
+            const uint64_t y = (xa[f] >> (4 * s + d)) & 0x0101010101010101ull;
+            owa[0][f][d] = (int)(uint32_t)y;
+            owa[1][f][d] = (int)(uint32_t)(y >> 32);
+          }
+#pragma unroll
+        for (int g = 0; g < RB; ++g)
+#pragma unroll
+          for (int d = 0; d < 4; ++d) {
+            const uint64_t y = (xb[g] >> (4 * s + d)) & 0x0101010101010101ull;
+            owb[0][g][d] = (int)(uint32_t)y;
+            owb[1][g][d] = (int)(uint32_t)(y >> 32);
+          }
+#pragma unroll
+        for (int hw = 0; hw < 2; ++hw)
+#pragma unroll
+          for (int f = 0; f < RA; ++f)
+#pragma unroll
+            for (int g = 0; g < RB; ++g)
+              acc[f][g] = __builtin_amdgcn_mfma_i32_32x32x32_i8(owa[hw][f], owb[hw][g], acc[f][g],
+                                                                0, 0, 0);
+        continue;
+      }
       // The rows of one side (the longer, or with SHORT the shorter) expand both 32-bit
       // halves of a word at once: one 64-bit shift and two masks give dword d of each
       // half, where the 32-bit form takes two shifts and two masks.  Holding both halves
@@ -303,7 +333,7 @@ __device__ __forceinline__ void epilogue(const typename Acc<FMT>::type (&acc)[RA
 // compiler knows every load in flight, and NB register buffers keep the words
 // of step st + NB - 1 in flight while step st computes.
 template <int SEMI, int RA, int RB, int KV, int FMT, int NB = 2, int STEPS = 0, bool WIDE = true,
-          bool SHORT = false>
+          bool SHORT = false, bool BOTH = false>
 __device__ __forceinline__ void tile(const uint64_t* __restrict__ A, int64_t lda,
                                      const uint64_t* __restrict__ BT, int64_t ldbt,
                                      uint64_t* __restrict__ Cm, int64_t ldc, int64_t m,
@@ -368,7 +398,7 @@ __device__ __forceinline__ void tile(const uint64_t* __restrict__ A, int64_t lda
   };
   auto compute = [&](const uint64_t (&xa)[KV][RA], const uint64_t (&xb)[KV][RB]) {
 #pragma unroll
-    for (int v = 0; v < KV; ++v) mfma_word<SEMI, RA, RB, FMT, WIDE, SHORT>(xa[v], xb[v], acc);
+    for (int v = 0; v < KV; ++v) mfma_word<SEMI, RA, RB, FMT, WIDE, SHORT, BOTH>(xa[v], xb[v], acc);
   };
   if constexpr (STEPS > 0) {
     static_assert(STEPS >= NB, "an unrolled pipeline needs at least NB steps");
@@ -459,7 +489,7 @@ tail:
         for (int f = 0; f < RA; ++f) xa[f] = wi < kw ? arow[f][w - adv + v] : 0ull;
 #pragma unroll
         for (int g = 0; g < RB; ++g) xb[g] = wi < kw ? brow[g][w - adv + v] : 0ull;
-        mfma_word<SEMI, RA, RB, FMT, WIDE, SHORT>(xa, xb, acc);
+        mfma_word<SEMI, RA, RB, FMT, WIDE, SHORT, BOTH>(xa, xb, acc);
       }
     }
   }
