@@ -78,12 +78,11 @@ hipError_t launch_lds4(const LeafBatch& p, hipStream_t s) {
 }
 
 // DEEP: int8 leaves of the recursion's lengths (k = 2048 or 4096 bits, 16-byte
-// aligned) run a fully unrolled load pipeline with 64-bit operand expansion.  k = 4096:
-// 3 register buffers, the shorter side's rows (two of B^T) wide (6% fewer VALU
-// instructions, 2% faster; widening the longer side instead spilled and gained
-// nothing).  k = 2048: 2 buffers and both sides wide (13% fewer VALU instructions than
-// the shorter side alone, the n = 2^18 recursion 1-1.5% faster; with 3 buffers both
-// sides wide spill).  CHUNKED: aligned int8 leaves
+// aligned) run a fully unrolled load pipeline with two register buffers and both
+// operand sides expanded by 64-bit shifts: 18% fewer VALU instructions than the 32-bit
+// form, 13% fewer than widening the shorter side alone (with three buffers, which then
+// measured 1-1.5% slower at k = 2048 and 3.4% slower at k = 4096; both sides wide with
+// three buffers spill).  CHUNKED: aligned int8 leaves
 // run the 2-deep pipeline as a loop over fully unrolled chunks of 12 steps, which
 // leaves the compiler's conservative wait for outstanding loads at the loop's
 // back edge once per chunk instead of once per step pair.  All else takes the
@@ -109,8 +108,8 @@ hipError_t launch_t(const LeafBatch& p, hipStream_t s) {
       return hipGetLastError();
     }
     if (aligned16 && p.k == 4096) {
-      hipLaunchKernelGGL((leaf_mfma_kernel<SEMI, RA, RB, 2, FMT, 3, 16, true, true>), g, b, 0, s, p,
-                         tiles_m, tiles_n);
+      hipLaunchKernelGGL((leaf_mfma_kernel<SEMI, RA, RB, 2, FMT, 2, 16, true, false, true>), g, b, 0,
+                         s, p, tiles_m, tiles_n);
       return hipGetLastError();
     }
   }
